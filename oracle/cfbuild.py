@@ -1,0 +1,212 @@
+"""Convolution-function table (the CFCache of the paper's AWP framework).
+
+Paper: Table AWP-CFSETUP composes the kernel from the prolate spheroidal
+taper (PS), the antenna aperture term (A) and the W-term (W); the ConvFunc
+component computes c_ij and the CFCache holds the result (physical
+architecture section).  The construction itself is not given; the reading
+used here is:
+
+  screen   S(l_j, m_i) = a_j a_i T(l_j) T(m_i) [B(rho)] [W_k(l, m)] on the
+           (M+1) x (M+1) points l_j = j Lx / M, j = -M/2..M/2, Lx = nx dl
+           (likewise m), a_j = 1/2 at j = +-M/2 and 1 elsewhere (trapezoid
+           end weights: the screen stays even, so real even terms give a
+           real kernel and K_{-w} = conj K_w holds), with
+           T(l) = psi_0(c, 2 l / Lx), c = pi S_ps / 2            (PS term)
+           B(rho) = [2 J1(x)/x]^2, x = pi D nu_fg rho / c_light   (A term,
+                    power pattern of identical dishes, diagonal Mueller)
+           W_k = exp(-2 pi i w_k (sqrt(1 - l^2 - m^2) - 1)), 0 outside the
+                 unit circle, w_k = k w_max / (n_w - 1)            (W term)
+  kernel   K(n_u, n_v) = sum_{j,i} S e^{-2 pi i (n_u j + n_v i) / (O M)},
+           the length-O*M DFT of the zero-padded screen (numpy FFT here)
+  table    C[fg][k][o_v + O/2][o_u + O/2][t_v + h][t_u + h]
+             = conj K(o_u - O t_u, o_v - O t_v) / (M^2 T(0)^2)
+           for o in [-O/2, O/2] (O + 1 offsets) and t in [-h_k, h_k].
+
+With this normalisation the un-cropped tap sum of every offset is exactly 1.
+Storage forms: f64; f32 by round-to-nearest-even; f16 / bf16 as
+RNE(C * 2^e_k) with e_k per plane chosen so that the largest component
+magnitude times 2^e_k lies in [0.5, 1).
+"""
+
+from dataclasses import dataclass
+
+import numpy as np
+from scipy import special
+
+from .conventions import C_LIGHT, half_widths, plane_offsets, screen_size
+from .pswf import pswf_nystrom
+
+TERM_PS, TERM_W, TERM_A = 1, 2, 4
+
+
+@dataclass
+class OracleCF:
+    table: np.ndarray        # complex128, flat
+    plane_off: np.ndarray    # int64 [n_fg * n_w]
+    h: np.ndarray            # int32 [n_w]
+    O: int
+    n_w: int
+    n_fg: int
+    w_max: float
+    M: int
+    terms: int
+
+    def sub(self, fg, k, ov, ou):
+        """S x S sub-kernel for offset (ov, ou) in [-O/2, O/2]."""
+        S = 2 * int(self.h[k]) + 1
+        no = self.O + 1
+        base = int(self.plane_off[fg * self.n_w + k]) + \
+            ((ov + self.O // 2) * no + (ou + self.O // 2)) * S * S
+        return self.table[base:base + S * S].reshape(S, S)
+
+    def plane(self, fg, k):
+        S = 2 * int(self.h[k]) + 1
+        no = self.O + 1
+        base = int(self.plane_off[fg * self.n_w + k])
+        return self.table[base:base + no * no * S * S].reshape(no, no, S, S)
+
+
+def airy_power(x):
+    x = np.asarray(x, dtype=np.float64)
+    out = np.ones_like(x)
+    nz = x != 0
+    b = 2.0 * special.j1(x[nz]) / x[nz]
+    out[nz] = b * b
+    return out
+
+
+def screen(M, nx, ny, cell_l, cell_m, terms, ps_support, w_k, nu_fg, dish_m, psi=None,
+           shift=(0.0, 0.0)):
+    """(M+1) x (M+1) complex128 screen, rows = m (v axis), columns = l (u
+    axis), sample j at l = j Lx / M for j = -M/2..M/2, edge samples halved.
+    `shift` evaluates every term at (l - dl, m - dm) (used only by a test of
+    the pointing phasor)."""
+    Lx, Ly = nx * cell_l, ny * cell_m
+    j = np.arange(-(M // 2), M // 2 + 1)
+    l = j * Lx / M - shift[0]
+    m = j * Ly / M - shift[1]
+    a = np.ones(M + 1)
+    a[0] = a[-1] = 0.5
+    ll, mm = np.meshgrid(l, m)          # [i][j] = (m_i, l_j)
+    s = np.outer(a, a).astype(np.complex128)
+    if terms & TERM_PS:
+        if psi is None:
+            psi = pswf_nystrom(np.pi * ps_support / 2.0)[0]
+        s *= np.outer(psi(2.0 * m / Ly), psi(2.0 * l / Lx))
+    if terms & TERM_A:
+        rho = np.sqrt(ll * ll + mm * mm)
+        s *= airy_power(np.pi * dish_m * nu_fg * rho / C_LIGHT)
+    if terms & TERM_W:
+        r2 = ll * ll + mm * mm
+        inside = r2 < 1.0
+        n1 = np.zeros_like(r2)
+        n1[inside] = np.sqrt(1.0 - r2[inside]) - 1.0
+        wt = np.exp(-2j * np.pi * w_k * n1)
+        wt[~inside] = 0.0
+        s *= wt
+    return s
+
+
+def kernel_fft(scr, O):
+    """K[n_v mod OM, n_u mod OM] = sum_{i,j} S[i][j] e^{-2 pi i (n_u j + n_v i)/(OM)},
+    j, i = -M/2..M/2."""
+    M = scr.shape[0] - 1
+    N = O * M
+    pad = np.zeros((N, N), np.complex128)
+    idx = np.arange(-(M // 2), M // 2 + 1) % N
+    if O == 1:
+        # +M/2 and -M/2 coincide modulo M: their halves add
+        pad[np.ix_(idx[:-1], idx[:-1])] += scr[:-1, :-1]
+        pad[np.ix_(idx[:-1], [idx[-1]])] += scr[:-1, -1:]
+        pad[np.ix_([idx[-1]], idx)] += scr[-1:, :]
+    else:
+        pad[np.ix_(idx, idx)] = scr
+    return np.fft.fft2(pad)
+
+
+def crop_plane(K, M, O, h, t0_sq):
+    """[O+1][O+1][S][S] = conj K(o_u - O t_u, o_v - O t_v) / (M^2 T(0)^2)."""
+    N = O * M
+    o = np.arange(-(O // 2), O // 2 + 1)
+    t = np.arange(-h, h + 1)
+    n = (o[:, None] - O * t[None, :]) % N          # [o][t]
+    # K indexed [n_v][n_u]; output [ov][ou][tv][tu]
+    out = K[n[:, None, :, None], n[None, :, None, :]]
+    return np.conj(out) / (M * M * t0_sq)
+
+
+def build_cf(grid, cf, n_nodes=64):
+    """Build the FP64 table for a synth GridSetup / CFSetup pair."""
+    h = half_widths(cf.n_w, cf.h_min, cf.h_max)
+    M = screen_size(h, cf.screen_m)
+    O = cf.oversample
+    n_fg = cf.n_fg
+    off, total = plane_offsets(n_fg, h, O)
+    table = np.zeros(total, np.complex128)
+    psi = None
+    t0 = 1.0
+    if cf.terms & TERM_PS:
+        psi = pswf_nystrom(np.pi * cf.ps_support / 2.0, n_nodes)[0]
+        t0 = float(psi(0.0)[0])
+    for g in range(n_fg):
+        for k in range(cf.n_w):
+            w_k = k * cf.w_max / (cf.n_w - 1) if cf.n_w > 1 else 0.0
+            scr = screen(M, grid.nx, grid.ny, grid.cell_l, grid.cell_m, cf.terms,
+                         cf.ps_support, w_k, float(cf.fg_hz[g]), cf.dish_m, psi)
+            K = kernel_fft(scr, O)
+            pl = crop_plane(K, M, O, int(h[k]), t0 * t0)
+            base = int(off[g * cf.n_w + k])
+            table[base:base + pl.size] = pl.ravel()
+    return OracleCF(table=table, plane_off=off, h=h, O=O, n_w=cf.n_w, n_fg=n_fg,
+                    w_max=cf.w_max, M=M, terms=cf.terms)
+
+
+# --- storage forms ---------------------------------------------------------
+
+def plane_scale_exponents(ocf):
+    """e_k per (fg, k): largest component magnitude times 2^e in [0.5, 1)."""
+    out = np.zeros(ocf.n_fg * ocf.n_w, np.int32)
+    for g in range(ocf.n_fg):
+        for k in range(ocf.n_w):
+            p = ocf.plane(g, k)
+            mx = max(np.max(np.abs(p.real)), np.max(np.abs(p.imag)))
+            if mx == 0:
+                continue
+            _, e = np.frexp(mx)
+            out[g * ocf.n_w + k] = -int(e)
+    return out
+
+
+def round_bf16(x):
+    """Round-to-nearest-even of float64 values to 8 significant bits
+    (bfloat16 within its normal range), returned as float64."""
+    x = np.asarray(x, np.float64)
+    mant, ex = np.frexp(x)                 # x = mant * 2^ex, |mant| in [0.5, 1)
+    return np.ldexp(np.rint(mant * 256.0), ex - 8)
+
+
+def quantised_table(ocf, storage):
+    """The table as the given storage form decodes it, in float64/complex128:
+    'f64', 'f32', 'f16', 'bf16'."""
+    t = ocf.table
+    if storage == "f64":
+        return t.copy()
+    if storage == "f32":
+        return t.astype(np.complex64).astype(np.complex128)
+    ex = plane_scale_exponents(ocf)
+    out = np.empty_like(t)
+    for g in range(ocf.n_fg):
+        for k in range(ocf.n_w):
+            S = 2 * int(ocf.h[k]) + 1
+            base = int(ocf.plane_off[g * ocf.n_w + k])
+            n = (ocf.O + 1) ** 2 * S * S
+            e = int(ex[g * ocf.n_w + k])
+            v = np.ldexp(t[base:base + n].real, e), np.ldexp(t[base:base + n].imag, e)
+            if storage == "f16":
+                q = [a.astype(np.float16).astype(np.float64) for a in v]
+            elif storage == "bf16":
+                q = [round_bf16(a) for a in v]
+            else:
+                raise ValueError(storage)
+            out[base:base + n] = np.ldexp(q[0], -e) + 1j * np.ldexp(q[1], -e)
+    return out
