@@ -1,0 +1,249 @@
+/*
+ * lr.h -- C ABI of the MI355X (gfx950) convolutional gridding / degridding
+ * library.
+ *
+ * The operations follow the paper's statement of the imaging problem
+ * (Bhatnagar et al., "An Algorithm Architecture for Radio Interferometric
+ * Data Processing"):
+ *   degridding D(c_ij)   Eq. ME-MOD-GRIDDED: model visibilities resampled off
+ *                        the regular grid through the kernels c_ij;
+ *   gridding G(c_ij)     Eq. IMAGE-MOD: weighted visibilities w_ij V_ij
+ *                        accumulated onto the regular grid (the "reverse
+ *                        operator" of D);
+ *   kernels c_ij         Eq. CIJ and Table AWP-CFSETUP: oversampled PS, A and
+ *                        W convolution functions held in a CF cache (the
+ *                        PreCompute component), with the per-baseline
+ *                        pointing-offset phasor applied on the fly;
+ *   summations over t, nu  Eq. ResIm and the OutTransform component: a channel
+ *                        map chooses accumulation (continuum) or gather
+ *                        (cube planes).
+ *
+ * Conventions (the paper leaves them open; these are this library's):
+ *   - A sample is one (row, channel, polarisation) complex visibility.
+ *   - Grid layout [nplane][npol][ny][nx], complex interleaved (re, im), x
+ *     fastest.  u = 0 lies at pixel nx/2, v = 0 at ny/2; the uv cell is
+ *     du = 1/(nx cell_l).
+ *   - Per channel the host forms, in FP64 left to right:
+ *       s = nu/c;  kx = ((s nx) cell_l) O;  ky = ((s ny) cell_m) O;
+ *       kw = s ((n_w - 1)/w_max) (0 if n_w == 1);  ox = (nx/2) O + 1/2.
+ *     Per sample the device forms X = fma(u, kx, ox) (one rounding), drops
+ *     the sample unless 0 <= X < nx O, takes q = floor(X), p = floor((q +
+ *     O/2)/O), o = q - p O in [-O/2, O/2); the w-plane is
+ *     k = floor(fma(|w|, kw, 1/2)) and the kernel is conjugated when w < 0
+ *     (n_w > 1).  These integers are bit-exact with the CPU oracle.
+ *   - Support of w-plane k: S_k = 2 h_k + 1, h_k = h_min + floor((2 (h_max -
+ *     h_min) k + n_w - 1) / (2 (n_w - 1))).  A sample whose footprint
+ *     [p - h_k, p + h_k] leaves [0, N-1] (PSF: [1, N-1]) on either axis, or
+ *     whose k exceeds n_w - 1, is dropped and counted, never clamped.
+ *   - A sample is flagged when its weight is 0 or its channel maps to a
+ *     negative plane.  counters[3] = {kept, flagged, dropped} (int64).
+ *
+ * Memory: every device buffer is caller-owned.  Sizes come from the *_bytes
+ * queries.  lr_cf and lr_plan handles are small host objects that describe
+ * caller-owned device blobs.  Outputs grid, psf_grid, sumwt and counters
+ * are ACCUMULATED (+=), so partitions of the data can be gridded into the
+ * same grid; the caller zeroes them.  lr_degrid OVERWRITES vis.
+ *
+ * Errors: every entry point returns an lr_status; host-side validation runs
+ * before anything is enqueued and leaves outputs untouched.  Work is
+ * asynchronous on the given stream (NULL = the null stream).  A device
+ * fault surfaces as LR_E_DEVICE on a later call or at synchronisation.
+ * lr_last_error() gives a thread-local message for the last failure.
+ * Calls are re-entrant; concurrent calls must not share outputs or scratch.
+ */
+#ifndef LR_H
+#define LR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t *lr_stream;     /* a hipStream_t */
+
+typedef enum {
+    LR_OK = 0,
+    LR_E_ARG = -1,        /* a malformed descriptor or pointer */
+    LR_E_DTYPE = -2,      /* CF storage does not match the precision form */
+    LR_E_WORKSPACE = -3,  /* a caller buffer is smaller than required */
+    LR_E_CF = -4,         /* the CF blob is not a valid table for this spec */
+    LR_E_DEVICE = -5,     /* a HIP runtime error */
+    LR_E_RANGE = -6       /* a size beyond the supported range */
+} lr_status;
+
+/* Precision forms.  LR_F64: complex128 vis and grid, float64 weights, f64 CF.
+ * LR_F32: complex64 vis and grid, float32 weights, f32 CF.  LR_F32_CF16 /
+ * LR_F32_CFBF16: as LR_F32 with the CF stored as fp16 / bf16 pairs scaled by
+ * 2^e per plane, accumulation in FP32.  In every form the uvw scaling, the
+ * index map, the pointing-phasor argument and sumwt are FP64. */
+typedef enum { LR_F64 = 0, LR_F32 = 1, LR_F32_CF16 = 2, LR_F32_CFBF16 = 3 } lr_precision;
+
+/* CF terms, Table AWP-CFSETUP: PS = anti-aliasing prolate spheroidal taper,
+ * W = W-term, A = antenna aperture (Airy power pattern). */
+enum { LR_TERM_PS = 1u, LR_TERM_W = 2u, LR_TERM_A = 4u };
+
+typedef struct {
+    int32_t nx, ny;        /* even, 8 .. 16384 */
+    int32_t npol;          /* correlations: 1, 2 or 4 */
+    int32_t nplane;        /* output planes (cube channels or 1) */
+    double cell_l, cell_m; /* image cell, radians */
+} lr_grid_spec;
+
+/* Kernel construction (Table AWP-CFSETUP; the CFCache / ConvFunc
+ * components).  The screen T(l) T(m) [B] [W_k] is sampled on (M+1)^2 points
+ * spanning the image with trapezoid end weights, transformed by a length O M
+ * DFT, cropped to S_k x S_k taps for each of the (O+1)^2 offsets
+ * o in [-O/2, O/2], divided by M^2 and conjugated. */
+typedef struct {
+    uint32_t terms;        /* LR_TERM_* bit set, nonzero */
+    int32_t oversample;    /* O, even, 2 .. 126 */
+    int32_t ps_support;    /* S_ps of the PS taper: c = pi S_ps / 2 */
+    int32_t n_w;           /* w-planes, 1 .. 255 */
+    double w_max;          /* wavelengths mapped to plane n_w - 1 (n_w > 1) */
+    int32_t h_min, h_max;  /* support half-widths, 0 <= h_min <= h_max <= 128 */
+    int32_t n_fg;          /* A-term frequency groups, 1 .. 127 */
+    const double *fg_hz;   /* host [n_fg]: frequency of each group's A-term */
+    double dish_m;         /* Airy dish diameter (A term) */
+    int32_t screen_m;      /* M, even; 0 = smallest even >= 2 S_max */
+    lr_precision storage;  /* element type of the table */
+} lr_cf_spec;
+
+typedef struct lr_cf lr_cf;       /* host handle over a caller-owned device blob */
+typedef struct lr_plan lr_plan;   /* host handle over a caller-owned device blob */
+
+/* Visibility data.  Device pointers unless noted. */
+typedef struct {
+    int64_t nrow;
+    int32_t nchan, npol, nant;
+    const double *uvw;          /* [nrow][3] metres, FP64 */
+    const double *freq_hz;      /* host [nchan] */
+    const int32_t *chan_plane;  /* host [nchan]: output plane, < 0 = skip */
+    const int32_t *chan_fg;     /* host [nchan] A-term group, or NULL = 0 */
+    void *vis;                  /* [nrow][nchan][npol] complex128 | complex64 */
+    const void *weight;         /* same shape, float64 | float32; 0 = flagged.
+                                   lr_degrid accepts NULL (nothing flagged) */
+    const int32_t *ant1, *ant2; /* [nrow], or NULL: no pointing phasor */
+    const double *ant_dlm;      /* [nant][2] pointing offsets (rad), or NULL */
+    const lr_plan *plan;        /* binning from lr_plan_build, or NULL */
+} lr_vis;
+
+/* ---- sizes ---------------------------------------------------------------- */
+
+/* Bytes of the device blob lr_cf_build fills (header + table); 0 when the
+ * specs are invalid (lr_last_error says why). */
+size_t lr_cf_bytes(const lr_cf_spec *spec, const lr_grid_spec *grid);
+
+enum { LR_OP_CF_BUILD = 0, LR_OP_GRID = 1, LR_OP_DEGRID = 2, LR_OP_PSF = 3,
+       LR_OP_SUMWT = 4 };
+
+/* Device scratch bytes an operation needs.  For LR_OP_CF_BUILD, vis may be
+ * NULL.  For the visibility operations the figure covers a transient plan
+ * when vis->plan is NULL.  0 on invalid arguments. */
+size_t lr_workspace_bytes(int op, const lr_cf_spec *spec, const lr_grid_spec *grid,
+                          const lr_vis *vis, lr_precision precision);
+
+/* ---- convolution functions (PreCompute) ------------------------------------- */
+
+/* Build the CF table for `spec` on `grid` into cf_buf (device, cf_bytes >=
+ * lr_cf_bytes) using `work` (device scratch, >= lr_workspace_bytes(
+ * LR_OP_CF_BUILD, ...)).  On LR_OK *out receives a host handle; the blob is
+ * immutable afterwards and may be shared by concurrent calls.  The handle
+ * must be released with lr_cf_free (which does not free cf_buf). */
+lr_status lr_cf_build(const lr_cf_spec *spec, const lr_grid_spec *grid, void *cf_buf,
+                      size_t cf_bytes, void *work, size_t work_bytes, lr_stream stream,
+                      lr_cf **out);
+
+/* Wrap an already built blob (same spec and grid) without recomputing it. */
+lr_status lr_cf_attach(const lr_cf_spec *spec, const lr_grid_spec *grid, void *cf_buf,
+                       size_t cf_bytes, lr_cf **out);
+
+void lr_cf_free(lr_cf *cf);
+
+/* Per-plane storage exponent e_k (table entries are C * 2^e_k) read back to
+ * the host into exps[n_fg * n_w]; synchronises the stream. */
+lr_status lr_cf_scale_exponents(const lr_cf *cf, int32_t *exps, lr_stream stream);
+
+/* Where the table lives in the blob: byte offset of element 0, bytes per
+ * complex element (16 f64, 8 f32, 4 fp16/bf16 pair), element count, and the
+ * element offset of every plane (fg, k) in plane_off[n_fg * n_w] (may be
+ * NULL).  The table is laid out [fg][k][o_v + O/2][o_u + O/2][t_v + h_k]
+ * [t_u + h_k], o in [-O/2, O/2]. */
+lr_status lr_cf_layout(const lr_cf *cf, size_t *table_offset, size_t *elem_bytes,
+                       int64_t *n_elems, int64_t *plane_off);
+
+/* ---- binning (PreSolvePrep) ------------------------------------------------ */
+
+/* Bytes of the device blob a plan needs for this data. */
+size_t lr_plan_bytes(const lr_cf *cf, const lr_vis *vis, int psf);
+
+/* Map every (row, channel), drop what leaves the grid, sort the rest by
+ * (plane, CF plane, w-plane, conj, pixel, offset) and merge samples whose
+ * kernel and footprint are identical into groups.  The plan depends on uvw,
+ * frequencies, channel maps, the CF geometry and (with a pointing phasor)
+ * the antenna ids, never on visibilities or weights.  psf != 0 builds the
+ * plan for the PSF footprint rule.  Synchronises the stream once (group and
+ * task counts come back to the host).  buf must stay alive while the plan
+ * is used; release the handle with lr_plan_free. */
+lr_status lr_plan_build(const lr_cf *cf, const lr_vis *vis, int psf, void *buf,
+                        size_t bytes, lr_stream stream, lr_plan **out);
+
+void lr_plan_free(lr_plan *plan);
+
+/* Number of groups, kept (row, channel) pairs and total pairs of a plan,
+ * and the kernel taps its groups cover, sum over groups of S_k^2 (the
+ * gridder and degridder each do one complex multiply-add per tap and
+ * polarisation). */
+lr_status lr_plan_info(const lr_plan *plan, int64_t *n_groups, int64_t *n_kept,
+                       int64_t *n_pairs, int64_t *taps);
+
+/* Diagnostic timing hook: the next lr_grid / lr_make_psf / lr_degrid on the
+ * calling thread records `start` (a hipEvent_t) on its stream just before
+ * its main kernel (the gridder or the degridder) and `stop` just after it,
+ * then forgets both.  NULL, NULL clears a pending request. */
+lr_status lr_set_profile_events(void *start, void *stop);
+
+/* ---- the hot path ------------------------------------------------------------ */
+
+/* Gridding G (Eq. IMAGE-MOD): grid[P][pol][p_v + t_v][p_u + t_u] +=
+ * Ct(o, t) phi(t) W V for every kept sample, Ct = C or conj C (w < 0),
+ * phi = pointing phasor (Eq. CIJ) when ant ids and offsets are given.
+ * sumwt [nplane][npol] (FP64) += W over kept samples; counters += class
+ * counts.  sumwt and counters may be NULL. */
+lr_status lr_grid(const lr_cf *cf, const lr_vis *vis, lr_precision precision, void *grid,
+                  double *sumwt, int64_t *counters, void *work, size_t work_bytes,
+                  lr_stream stream);
+
+/* Degridding D (Eq. ME-MOD-GRIDDED): vis = sum_t conj(Ct(o, t) phi(t)) grid[...]
+ * for kept samples; flagged and dropped samples are written as 0.  No
+ * weights enter the sum.  counters may be NULL. */
+lr_status lr_degrid(const lr_cf *cf, lr_vis *vis, lr_precision precision, const void *grid,
+                    int64_t *counters, void *work, size_t work_bytes, lr_stream stream);
+
+/* PSF: psf_grid += 1/2 (g + H g), g = the gridding of unit visibilities with
+ * weights W under the PSF footprint rule, (H g)[i][j] = conj g[ny-i][nx-j].
+ * The result is Hermitian, so its image is real.  vis->vis is not read. */
+lr_status lr_make_psf(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
+                      void *psf_grid, double *sumwt, int64_t *counters, void *work,
+                      size_t work_bytes, lr_stream stream);
+
+/* Sum of weights per (plane, pol) in FP64 and class counts, under the
+ * gridding footprint rule. */
+lr_status lr_sumwt(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
+                   double *sumwt, int64_t *counters, void *work, size_t work_bytes,
+                   lr_stream stream);
+
+/* Test hook: the index map of every (row, channel) as int32
+ * out[nrow][nchan][8] = {p_u, p_v, o_u, o_v, k, conj, keep, fg} (device). */
+lr_status lr_debug_map(const lr_cf *cf, const lr_vis *vis, int psf, int32_t *out,
+                       lr_stream stream);
+
+const char *lr_status_str(lr_status s);
+const char *lr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LR_H */

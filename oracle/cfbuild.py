@@ -17,7 +17,7 @@ used here is:
            W_k = exp(-2 pi i w_k (sqrt(1 - l^2 - m^2) - 1)), 0 outside the
                  unit circle, w_k = k w_max / (n_w - 1)            (W term)
   kernel   K(n_u, n_v) = sum_{j,i} S e^{-2 pi i (n_u j + n_v i) / (O M)},
-           the length-O*M DFT of the zero-padded screen (numpy FFT here)
+           the length-O*M DFT of the zero-padded screen (library FFT here)
   table    C[fg][k][o_v + O/2][o_u + O/2][t_v + h][t_u + h]
              = conj K(o_u - O t_u, o_v - O t_v) / (M^2 T(0)^2)
            for o in [-O/2, O/2] (O + 1 offsets) and t in [-h_k, h_k].
@@ -31,6 +31,7 @@ magnitude times 2^e_k lies in [0.5, 1).
 from dataclasses import dataclass
 
 import numpy as np
+from scipy import fft as sfft
 from scipy import special
 
 from .conventions import C_LIGHT, half_widths, plane_offsets, screen_size
@@ -100,7 +101,8 @@ def screen(M, nx, ny, cell_l, cell_m, terms, ps_support, w_k, nu_fg, dish_m, psi
         r2 = ll * ll + mm * mm
         inside = r2 < 1.0
         n1 = np.zeros_like(r2)
-        n1[inside] = np.sqrt(1.0 - r2[inside]) - 1.0
+        # sqrt(1 - r^2) - 1 written without cancellation
+        n1[inside] = -r2[inside] / (1.0 + np.sqrt(1.0 - r2[inside]))
         wt = np.exp(-2j * np.pi * w_k * n1)
         wt[~inside] = 0.0
         s *= wt
@@ -121,7 +123,7 @@ def kernel_fft(scr, O):
         pad[np.ix_([idx[-1]], idx)] += scr[-1:, :]
     else:
         pad[np.ix_(idx, idx)] = scr
-    return np.fft.fft2(pad)
+    return sfft.fft2(pad, workers=-1)
 
 
 def crop_plane(K, M, O, h, t0_sq):
@@ -135,8 +137,9 @@ def crop_plane(K, M, O, h, t0_sq):
     return np.conj(out) / (M * M * t0_sq)
 
 
-def build_cf(grid, cf, n_nodes=64):
-    """Build the FP64 table for a synth GridSetup / CFSetup pair."""
+def build_cf(grid, cf, n_nodes=64, planes=None):
+    """Build the FP64 table for a synth GridSetup / CFSetup pair.  `planes`
+    (a set of (fg, k)) restricts the work to those planes; the others stay 0."""
     h = half_widths(cf.n_w, cf.h_min, cf.h_max)
     M = screen_size(h, cf.screen_m)
     O = cf.oversample
@@ -150,6 +153,8 @@ def build_cf(grid, cf, n_nodes=64):
         t0 = float(psi(0.0)[0])
     for g in range(n_fg):
         for k in range(cf.n_w):
+            if planes is not None and (g, k) not in planes:
+                continue
             w_k = k * cf.w_max / (cf.n_w - 1) if cf.n_w > 1 else 0.0
             scr = screen(M, grid.nx, grid.ny, grid.cell_l, grid.cell_m, cf.terms,
                          cf.ps_support, w_k, float(cf.fg_hz[g]), cf.dish_m, psi)

@@ -1,0 +1,97 @@
+"""Differentiable degridding.
+
+Eq. ME-MOD-GRIDDED predicts model visibilities as V = D F I (degridding D
+of the Fourier transform F of the image); Eq. ImChisq is the weighted chi^2
+of V against the data and Eq. ResIm states that its gradient is the
+residual image F^dagger G W (V - V_model).  Here D is the forward pass
+(lr_degrid) and its hand-written adjoint, unit-weight gridding G_1
+(lr_grid with weights 1 on unflagged samples), is the backward pass: for
+the complex-linear map y = D x, PyTorch's vector-Jacobian product is
+D^H grad_y = G_1 grad_y.
+
+F (centred, unnormalised, image -> grid with exp(-2 pi i (ul + vm))) and
+the grid-correction division lie outside the gridding hot path and use
+torch.fft.
+"""
+
+import torch
+
+from . import lr
+
+
+class DegridOp:
+    """Everything a differentiable degrid needs besides the grid: the CF,
+    the visibility descriptor (uvw, channels, flags), precision and the
+    workspaces, kept resident between calls."""
+
+    def __init__(self, cf, vis, precision, plan=True):
+        self.cf = cf
+        self.p = precision
+        cdt = torch.complex128 if precision == lr.LR_F64 else torch.complex64
+        rdt = torch.float64 if precision == lr.LR_F64 else torch.float32
+        self.cdt, self.rdt = cdt, rdt
+        dev = vis.uvw.device
+        shape = (vis.nrow, vis.nchan, vis.npol)
+        # flags come from the weights; the operator itself carries no weights
+        self.mask = (vis.weight != 0).to(rdt) if vis.weight is not None else \
+            torch.ones(shape, dtype=rdt, device=dev)
+        base = vis.with_(vis=None, weight=self.mask, plan=None)
+        self.plan = lr.Plan(cf, base) if plan else None
+        self.vis = base.with_(plan=self.plan)
+        self.shape = shape
+        g = cf.grid
+        self.grid_shape = (g.nplane, g.npol, g.ny, g.nx)
+        self.work_d = lr._work(lr.LR_OP_DEGRID, cf, self.vis, precision, None)
+        self.work_g = lr._work(lr.LR_OP_GRID, cf, self.vis, precision, None)
+
+    def degrid(self, grid):
+        out = torch.empty(self.shape, dtype=self.cdt, device=grid.device)
+        lr.lr_degrid(self.cf, self.vis.with_(vis=out), self.p, grid.contiguous(),
+                     work=self.work_d)
+        return out
+
+    def grid_adjoint(self, v):
+        g = torch.zeros(self.grid_shape, dtype=self.cdt, device=v.device)
+        lr.lr_grid(self.cf, self.vis.with_(vis=v.contiguous()), self.p, g, work=self.work_g)
+        return g
+
+
+class Degrid(torch.autograd.Function):
+    """V = D(grid); backward: grad_grid = G_1(grad_V)."""
+
+    @staticmethod
+    def forward(ctx, grid, op):
+        ctx.op = op
+        return op.degrid(grid.to(op.cdt))
+
+    @staticmethod
+    def backward(ctx, grad_v):
+        return ctx.op.grid_adjoint(grad_v.to(ctx.op.cdt)), None
+
+
+def centred_fft2(img):
+    """F: grid[v][u] = sum_pix img[m][l] exp(-2 pi i (u l + v m)), pixel n/2 at 0."""
+    return torch.fft.fftshift(torch.fft.fft2(torch.fft.ifftshift(img, dim=(-2, -1))),
+                              dim=(-2, -1))
+
+
+def centred_ifft2(grid):
+    """F^dagger, unnormalised."""
+    n = grid.shape[-1] * grid.shape[-2]
+    return torch.fft.fftshift(torch.fft.ifft2(torch.fft.ifftshift(grid, dim=(-2, -1))),
+                              dim=(-2, -1)) * n
+
+
+def predict(image, op, gamma=None):
+    """Model visibilities D F (gamma * image) for a real image
+    [nplane, npol, ny, nx]; gamma is the grid-correction weight (1/gcf) or
+    None."""
+    x = image if gamma is None else image * gamma
+    grid = centred_fft2(x.to(op.cdt))
+    return Degrid.apply(grid, op)
+
+
+def chi2(image, op, vis_obs, weight, gamma=None):
+    """Eq. ImChisq: sum W |V_obs - D F gamma I|^2."""
+    r = vis_obs - predict(image, op, gamma)
+    return (weight * (r.real ** 2 + r.imag ** 2)).sum()

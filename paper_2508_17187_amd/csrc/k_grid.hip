@@ -1,0 +1,535 @@
+// The gridding / degridding hot path on gfx950 (no MFMA: the work is a
+// scatter / gather, not a dense contraction).
+//
+// Gridding G (Eq. IMAGE-MOD) runs in two kernels over a binning plan:
+//   presum   for every group of samples that share plane, kernel and
+//            footprint, A_g = sum W V (exact regrouping of the sum; FP32 or
+//            FP64), together with the class counters and FP64 sum of weights;
+//   grid     one wavefront task = 64 of the S*S residue classes of the
+//            support (cell x mod S, cell y mod S) over a run of groups of one
+//            w-plane sorted by pixel.  Each lane owns one grid cell at a time
+//            and accumulates Ct(o, t) phi(t) A_g for it in registers; only when
+//            the footprint moves off that cell does the lane flush its
+//            accumulator to HBM with atomics.  Group data are wave-uniform
+//            (scalar loads), the kernel tap is one vector load per lane.
+// Degridding D (Eq. ME-MOD-GRIDDED):
+//   degrid   one wavefront per group gathers sum_t conj(Ct phi) grid over the
+//            footprint (lanes over taps, coalesced along t_u) and reduces
+//            across lanes;
+//   expand   writes each group's value to every sample of the group (0 for
+//            flagged, skipped and dropped samples).
+#include "lr_internal.h"
+#include "lr_launch.h"
+
+namespace lr {
+
+template <typename T>
+struct cpx {
+    T x, y;
+};
+
+__global__ void k_zero(uint4 *p, int64_t n16, uint8_t *tail, int ntail) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) p[i] = make_uint4(0, 0, 0, 0);
+    if (i < ntail) tail[i] = 0;
+}
+
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    int64_t n16 = (int64_t)(bytes / 16);
+    int ntail = (int)(bytes - n16 * 16);
+    int64_t n = n16 > ntail ? n16 : ntail;
+    hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint4 *)p,
+                       n16, (uint8_t *)p + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// CF element access; f16 / bf16 pairs are decoded exactly to FP32 and
+// multiplied by the plane's 2^-e.
+template <int ST>
+struct CFElem;
+template <>
+struct CFElem<LR_F64> {
+    typedef double T;
+    __device__ static cpx<double> load(const void *t, int64_t i, float) {
+        double2 v = ((const double2 *)t)[i];
+        return {v.x, v.y};
+    }
+};
+template <>
+struct CFElem<LR_F32> {
+    typedef float T;
+    __device__ static cpx<float> load(const void *t, int64_t i, float) {
+        float2 v = ((const float2 *)t)[i];
+        return {v.x, v.y};
+    }
+};
+template <>
+struct CFElem<LR_F32_CF16> {
+    typedef float T;
+    __device__ static cpx<float> load(const void *t, int64_t i, float sc) {
+        uint32_t b = ((const uint32_t *)t)[i];
+        _Float16 lo, hi;
+        uint16_t l16 = (uint16_t)(b & 0xffffu), h16 = (uint16_t)(b >> 16);
+        __builtin_memcpy(&lo, &l16, 2);
+        __builtin_memcpy(&hi, &h16, 2);
+        return {(float)lo * sc, (float)hi * sc};
+    }
+};
+template <>
+struct CFElem<LR_F32_CFBF16> {
+    typedef float T;
+    __device__ static cpx<float> load(const void *t, int64_t i, float sc) {
+        uint32_t b = ((const uint32_t *)t)[i];
+        return {__uint_as_float(b << 16) * sc, __uint_as_float(b & 0xffff0000u) * sc};
+    }
+};
+
+template <typename T>
+__device__ __forceinline__ void cmac(cpx<T> &acc, const cpx<T> &c, const cpx<T> &a) {
+    acc.x = fma(c.x, a.x, acc.x);
+    acc.x = fma(-c.y, a.y, acc.x);
+    acc.y = fma(c.x, a.y, acc.y);
+    acc.y = fma(c.y, a.x, acc.y);
+}
+
+// conj(c) * g accumulated
+template <typename T>
+__device__ __forceinline__ void cmac_conj(cpx<T> &acc, const cpx<T> &c, const cpx<T> &g) {
+    acc.x = fma(c.x, g.x, acc.x);
+    acc.x = fma(c.y, g.y, acc.x);
+    acc.y = fma(c.x, g.y, acc.y);
+    acc.y = fma(-c.y, g.x, acc.y);
+}
+
+// Pointing phasor of tap (tu, tv): f exp(-2 pi i ((tu O - ou) bu + (tv O - ov) bv)),
+// argument formed and reduced modulo 1 in FP64.
+template <typename T>
+__device__ __forceinline__ cpx<T> phasor(const GroupMeta &gm, int tu, int tv, int O) {
+    double a = fma((double)(tu * O - gm.ou), gm.bu, (double)(tv * O - gm.ov) * gm.bv);
+    a = a - rint(a);
+    cpx<T> r;
+    if (sizeof(T) == 8) {
+        double s, c;
+        sincospi(-2.0 * a, &s, &c);
+        r.x = (T)(gm.f * c);
+        r.y = (T)(gm.f * s);
+    } else {
+        float s, c;
+        sincospif((float)(-2.0 * a), &s, &c);
+        r.x = (T)((float)gm.f * c);
+        r.y = (T)((float)gm.f * s);
+    }
+    return r;
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(const cpx<T> &a, const cpx<T> &b) {
+    cpx<T> r;
+    r.x = a.x * b.x - a.y * b.y;
+    r.y = a.x * b.y + a.y * b.x;
+    return r;
+}
+
+__device__ __forceinline__ float wave_sum(float v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+__device__ __forceinline__ long long wave_sum_ll(long long v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+// presum + counters: one thread per group; then the non-kept pairs.
+template <typename T, int NPOL, bool UNIT, bool SUMS>
+__global__ __launch_bounds__(256) void k_presum(
+    int64_t n_groups, int64_t n_kept, int64_t n_pairs, const int32_t *order,
+    const int32_t *group_start, const GroupMeta *groups, const T *vis, const T *weight,
+    cpx<T> *A, double *sumwt, long long *counters) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    long long kept = 0, flagged = 0, dropped = 0;
+    double sw[NPOL];
+    int plane = -1;
+    for (int p = 0; p < NPOL; ++p) sw[p] = 0.0;
+    if (g < n_groups) {
+        int32_t i0 = group_start[g], i1 = group_start[g + 1];
+        plane = groups[g].plane;
+        cpx<T> acc[NPOL];
+        for (int p = 0; p < NPOL; ++p) acc[p] = {(T)0, (T)0};
+        for (int32_t i = i0; i < i1; ++i) {
+            int64_t pair = order[i];
+            for (int p = 0; p < NPOL; ++p) {
+                T W = weight ? weight[pair * NPOL + p] : (T)1;
+                if (W != (T)0) {
+                    ++kept;
+                    sw[p] += (double)W;
+                    if (SUMS) {
+                        if (UNIT) {
+                            acc[p].x += W;
+                        } else {
+                            const T *v = vis + 2 * (pair * NPOL + p);
+                            acc[p].x = fma(W, v[0], acc[p].x);
+                            acc[p].y = fma(W, v[1], acc[p].y);
+                        }
+                    }
+                } else {
+                    ++flagged;
+                }
+            }
+        }
+        if (SUMS)
+            for (int p = 0; p < NPOL; ++p) A[g * NPOL + p] = acc[p];
+    }
+    // pairs that were dropped or skipped at binning
+    int64_t nt = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = n_kept + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pairs;
+         i += nt) {
+        int32_t v = order[i];
+        bool skipped = (v >> 30) & 1;
+        int64_t pair = v & ~(1 << 30);
+        for (int p = 0; p < NPOL; ++p) {
+            T W = weight ? weight[pair * NPOL + p] : (T)1;
+            if (skipped || W == (T)0) ++flagged; else ++dropped;
+        }
+    }
+    if (counters) {
+        kept = wave_sum_ll(kept);
+        flagged = wave_sum_ll(flagged);
+        dropped = wave_sum_ll(dropped);
+        if ((threadIdx.x & 63) == 0) {
+            if (kept) atomicAdd((unsigned long long *)&counters[0], (unsigned long long)kept);
+            if (flagged) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)flagged);
+            if (dropped) atomicAdd((unsigned long long *)&counters[2], (unsigned long long)dropped);
+        }
+    }
+    if (sumwt) {
+        // one atomic per wavefront when every lane with a group shares its plane
+        unsigned long long has = __ballot(plane >= 0);
+        int lead = has ? __shfl(plane, __ffsll((long long)has) - 1) : -1;
+        bool uniform = __all(plane < 0 || plane == lead);
+        if (uniform) {
+            for (int p = 0; p < NPOL; ++p) {
+                double s = wave_sum(sw[p]);
+                if ((threadIdx.x & 63) == 0 && lead >= 0 && s != 0.0)
+                    atomicAdd(&sumwt[lead * NPOL + p], s);
+            }
+        } else if (plane >= 0) {
+            for (int p = 0; p < NPOL; ++p)
+                if (sw[p] != 0.0) atomicAdd(&sumwt[plane * NPOL + p], sw[p]);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+struct GridArgs {
+    const GroupMeta *groups;
+    const int32_t *r_g0, *r_toff;
+    int64_t n_ranges, n_tasks;
+    const void *A;
+    void *grid;
+    CFView cf;
+    int32_t nx, ny;
+    int64_t pol_stride;   // nx * ny
+};
+
+template <typename T, int ST, int NPOL, bool PO, bool PSF>
+__global__ __launch_bounds__(256) void k_grid(GridArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (t >= a.n_tasks) return;
+    // range of this task: largest r with r_toff[r] <= t
+    int64_t lo = 0, hi = a.n_ranges;
+    while (hi - lo > 1) {
+        int64_t mid = (lo + hi) >> 1;
+        if (a.r_toff[mid] <= t) lo = mid; else hi = mid;
+    }
+    const int chunk = (int)(t - a.r_toff[lo]);
+    const int32_t g0 = a.r_g0[lo], g1 = a.r_g0[lo + 1];
+    const GroupMeta *G = a.groups;
+    const int k = G[g0].k;
+    const int h = a.cf.h[k];
+    const int S = 2 * h + 1;
+    const int cls = chunk * 64 + lane;
+    const bool valid = cls < S * S;
+    const int rx = cls % S, ry = cls / S;
+    const cpx<T> *Av = (const cpx<T> *)a.A;
+    T *grid = (T *)a.grid;
+
+    cpx<T> acc[NPOL];
+    for (int p = 0; p < NPOL; ++p) acc[p] = {(T)0, (T)0};
+    int64_t cur = -1, curbase = 0;
+    int cx = 0, cy = 0, dx = 0, dy = 0, tap = 0;
+    int64_t prev = -1;
+
+    auto flush = [&]() {
+        if (!valid || cur < 0) return;
+        for (int p = 0; p < NPOL; ++p) {
+            int64_t base = curbase + p * a.pol_stride;
+            T *q = grid + 2 * (base + (int64_t)cy * a.nx + cx);
+            if (PSF) {
+                T *m = grid + 2 * (base + (int64_t)(a.ny - cy) * a.nx + (a.nx - cx));
+                atomicAdd(q, (T)0.5 * acc[p].x);
+                atomicAdd(q + 1, (T)0.5 * acc[p].y);
+                atomicAdd(m, (T)0.5 * acc[p].x);
+                atomicAdd(m + 1, -(T)0.5 * acc[p].y);
+            } else {
+                atomicAdd(q, acc[p].x);
+                atomicAdd(q + 1, acc[p].y);
+            }
+        }
+    };
+
+    for (int32_t g = g0; g < g1; ++g) {
+        const GroupMeta gm = G[g];
+        if (gm.cell != prev) {
+            prev = gm.cell;
+            const int bx = gm.pu - h, by = gm.pv - h;
+            dx = rx - bx % S;
+            dx += dx < 0 ? S : 0;
+            dy = ry - by % S;
+            dy += dy < 0 ? S : 0;
+            const int64_t base = gm.cell - (int64_t)gm.pv * a.nx - gm.pu;
+            const int64_t nc = base + (int64_t)(by + dy) * a.nx + (bx + dx);
+            if (nc != cur) {
+                flush();
+                for (int p = 0; p < NPOL; ++p) acc[p] = {(T)0, (T)0};
+                cur = nc;
+                curbase = base;
+                cx = bx + dx;
+                cy = by + dy;
+            }
+            tap = dy * S + dx;
+        }
+        if (valid) {
+            const float sc = a.cf.scale[gm.fg * a.cf.n_w + k];
+            cpx<T> c = CFElem<ST>::load(a.cf.table, gm.cf_off + tap, sc);
+            if (gm.conj) c.y = -c.y;
+            if (PO) c = cmul(c, phasor<T>(gm, dx - h, dy - h, a.cf.O));
+            for (int p = 0; p < NPOL; ++p) {
+                const cpx<T> av = Av[(int64_t)g * NPOL + p];
+                cmac(acc[p], c, av);
+            }
+        }
+    }
+    flush();
+}
+
+// ---------------------------------------------------------------------------
+struct DegridArgs {
+    const GroupMeta *groups;
+    int64_t n_groups;
+    const void *grid;
+    void *Vg;
+    CFView cf;
+    int32_t nx, ny;
+    int64_t pol_stride;
+};
+
+template <typename T, int ST, int NPOL, bool PO>
+__global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    if (g >= a.n_groups) return;
+    const GroupMeta gm = a.groups[g];
+    const int h = a.cf.h[gm.k];
+    const int S = 2 * h + 1;
+    const float sc = a.cf.scale[gm.fg * a.cf.n_w + gm.k];
+    const T *grid = (const T *)a.grid;
+    const int64_t base = gm.cell - (int64_t)gm.pv * a.nx - gm.pu;
+    cpx<T> sum[NPOL];
+    for (int p = 0; p < NPOL; ++p) sum[p] = {(T)0, (T)0};
+    for (int tap = lane; tap < S * S; tap += 64) {
+        const int ty = tap / S, tx = tap - ty * S;
+        cpx<T> c = CFElem<ST>::load(a.cf.table, gm.cf_off + tap, sc);
+        if (gm.conj) c.y = -c.y;
+        if (PO) c = cmul(c, phasor<T>(gm, tx - h, ty - h, a.cf.O));
+        const int64_t cell = base + (int64_t)(gm.pv - h + ty) * a.nx + (gm.pu - h + tx);
+        for (int p = 0; p < NPOL; ++p) {
+            const T *q = grid + 2 * (cell + p * a.pol_stride);
+            cpx<T> gv = {q[0], q[1]};
+            cmac_conj(sum[p], c, gv);
+        }
+    }
+    cpx<T> *out = (cpx<T> *)a.Vg;
+    for (int p = 0; p < NPOL; ++p) {
+        T x = wave_sum(sum[p].x), y = wave_sum(sum[p].y);
+        if (lane == 0) out[g * NPOL + p] = {x, y};
+    }
+}
+
+template <typename T, int NPOL>
+__global__ __launch_bounds__(256) void k_expand(int64_t n_kept, int64_t n_pairs,
+                                                const int32_t *order, const int32_t *gidx,
+                                                const cpx<T> *Vg, cpx<T> *vis,
+                                                const T *weight) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs) return;
+    int64_t pair = order[i] & ~(1 << 30);
+    if (i < n_kept) {
+        int64_t g = gidx[i];
+        for (int p = 0; p < NPOL; ++p) {
+            bool flag = weight && weight[pair * NPOL + p] == (T)0;
+            vis[pair * NPOL + p] = flag ? cpx<T>{(T)0, (T)0} : Vg[g * NPOL + p];
+        }
+    } else {
+        for (int p = 0; p < NPOL; ++p) vis[pair * NPOL + p] = {(T)0, (T)0};
+    }
+}
+
+// ---------------------------------------------------------------------------
+static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename T, int NPOL>
+static hipError_t presum_t(const lr_plan *P, const VisArgs &v, void *A, double *sumwt,
+                           int64_t *counters, bool sums, hipStream_t s) {
+    int64_t n = P->n_groups > 0 ? P->n_groups : 1;
+    int64_t rest = P->n_pairs - P->n_kept;
+    if (rest > n) n = rest;
+    dim3 grd(nblk(n, 256)), blk(256);
+    const T *vis = (const T *)v.vis;
+    const T *wt = (const T *)v.weight;
+    long long *cnt = (long long *)counters;
+    if (!sums)
+        hipLaunchKernelGGL((k_presum<T, NPOL, false, false>), grd, blk, 0, s, P->n_groups,
+                           P->n_kept, P->n_pairs, P->order, P->group_start, P->groups, vis,
+                           wt, (cpx<T> *)A, sumwt, cnt);
+    else if (v.unit_vis)
+        hipLaunchKernelGGL((k_presum<T, NPOL, true, true>), grd, blk, 0, s, P->n_groups,
+                           P->n_kept, P->n_pairs, P->order, P->group_start, P->groups, vis,
+                           wt, (cpx<T> *)A, sumwt, cnt);
+    else
+        hipLaunchKernelGGL((k_presum<T, NPOL, false, true>), grd, blk, 0, s, P->n_groups,
+                           P->n_kept, P->n_pairs, P->order, P->group_start, P->groups, vis,
+                           wt, (cpx<T> *)A, sumwt, cnt);
+    return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t presum_np(const lr_plan *P, const VisArgs &v, void *A, double *sumwt,
+                            int64_t *counters, bool sums, hipStream_t s) {
+    switch (v.npol) {
+        case 1: return presum_t<T, 1>(P, v, A, sumwt, counters, sums, s);
+        case 2: return presum_t<T, 2>(P, v, A, sumwt, counters, sums, s);
+        default: return presum_t<T, 4>(P, v, A, sumwt, counters, sums, s);
+    }
+}
+
+hipError_t launch_presum(const lr_plan *P, const VisArgs &v, int precision, void *A,
+                         double *sumwt, int64_t *counters, int32_t, hipStream_t s) {
+    if (P->n_pairs == 0) return hipSuccess;
+    if (precision == LR_F64) return presum_np<double>(P, v, A, sumwt, counters, true, s);
+    return presum_np<float>(P, v, A, sumwt, counters, true, s);
+}
+
+hipError_t launch_counts(const lr_plan *P, const void *weight, int precision, int32_t npol,
+                         double *sumwt, int64_t *counters, int32_t, hipStream_t s) {
+    if (P->n_pairs == 0) return hipSuccess;
+    VisArgs v{nullptr, weight, npol, 0};
+    if (precision == LR_F64) return presum_np<double>(P, v, nullptr, sumwt, counters, false, s);
+    return presum_np<float>(P, v, nullptr, sumwt, counters, false, s);
+}
+
+template <typename T, int ST, int NPOL>
+static hipError_t grid_t(const GridArgs &ga, bool po, bool psf, hipStream_t s) {
+    dim3 grd(nblk(ga.n_tasks, 4)), blk(256);
+    if (po) {
+        if (psf) hipLaunchKernelGGL((k_grid<T, ST, NPOL, true, true>), grd, blk, 0, s, ga);
+        else hipLaunchKernelGGL((k_grid<T, ST, NPOL, true, false>), grd, blk, 0, s, ga);
+    } else {
+        if (psf) hipLaunchKernelGGL((k_grid<T, ST, NPOL, false, true>), grd, blk, 0, s, ga);
+        else hipLaunchKernelGGL((k_grid<T, ST, NPOL, false, false>), grd, blk, 0, s, ga);
+    }
+    return hipGetLastError();
+}
+
+template <typename T, int ST>
+static hipError_t grid_np(const GridArgs &ga, int npol, bool po, bool psf, hipStream_t s) {
+    switch (npol) {
+        case 1: return grid_t<T, ST, 1>(ga, po, psf, s);
+        case 2: return grid_t<T, ST, 2>(ga, po, psf, s);
+        default: return grid_t<T, ST, 4>(ga, po, psf, s);
+    }
+}
+
+hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
+                       int precision, int32_t npol, int32_t nx, int32_t ny, int32_t psf,
+                       hipStream_t s) {
+    if (P->n_tasks == 0) return hipSuccess;
+    GridArgs ga{P->groups, P->r_g0, P->r_toff, P->n_ranges, P->n_tasks, A, grid, cf, nx, ny,
+                (int64_t)nx * ny};
+    bool po = P->po != 0;
+    switch (precision) {
+        case LR_F64: return grid_np<double, LR_F64>(ga, npol, po, psf, s);
+        case LR_F32: return grid_np<float, LR_F32>(ga, npol, po, psf, s);
+        case LR_F32_CF16: return grid_np<float, LR_F32_CF16>(ga, npol, po, psf, s);
+        default: return grid_np<float, LR_F32_CFBF16>(ga, npol, po, psf, s);
+    }
+}
+
+template <typename T, int ST, int NPOL>
+static hipError_t degrid_t(const DegridArgs &da, bool po, hipStream_t s) {
+    dim3 grd(nblk(da.n_groups, 4)), blk(256);
+    if (po) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, true>), grd, blk, 0, s, da);
+    else hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false>), grd, blk, 0, s, da);
+    return hipGetLastError();
+}
+
+template <typename T, int ST>
+static hipError_t degrid_np(const DegridArgs &da, int npol, bool po, hipStream_t s) {
+    switch (npol) {
+        case 1: return degrid_t<T, ST, 1>(da, po, s);
+        case 2: return degrid_t<T, ST, 2>(da, po, s);
+        default: return degrid_t<T, ST, 4>(da, po, s);
+    }
+}
+
+hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
+                         int precision, int32_t npol, int32_t nx, int32_t ny, hipStream_t s) {
+    if (P->n_groups == 0) return hipSuccess;
+    DegridArgs da{P->groups, P->n_groups, grid, Vg, cf, nx, ny, (int64_t)nx * ny};
+    bool po = P->po != 0;
+    switch (precision) {
+        case LR_F64: return degrid_np<double, LR_F64>(da, npol, po, s);
+        case LR_F32: return degrid_np<float, LR_F32>(da, npol, po, s);
+        case LR_F32_CF16: return degrid_np<float, LR_F32_CF16>(da, npol, po, s);
+        default: return degrid_np<float, LR_F32_CFBF16>(da, npol, po, s);
+    }
+}
+
+template <typename T>
+static hipError_t expand_t(const lr_plan *P, const void *Vg, void *vis, const void *weight,
+                           int npol, hipStream_t s) {
+    dim3 grd(nblk(P->n_pairs, 256)), blk(256);
+    const cpx<T> *V = (const cpx<T> *)Vg;
+    cpx<T> *out = (cpx<T> *)vis;
+    const T *w = (const T *)weight;
+    switch (npol) {
+        case 1:
+            hipLaunchKernelGGL((k_expand<T, 1>), grd, blk, 0, s, P->n_kept, P->n_pairs,
+                               P->order, P->gidx, V, out, w);
+            break;
+        case 2:
+            hipLaunchKernelGGL((k_expand<T, 2>), grd, blk, 0, s, P->n_kept, P->n_pairs,
+                               P->order, P->gidx, V, out, w);
+            break;
+        default:
+            hipLaunchKernelGGL((k_expand<T, 4>), grd, blk, 0, s, P->n_kept, P->n_pairs,
+                               P->order, P->gidx, V, out, w);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_expand(const lr_plan *P, const void *Vg, void *vis, const void *weight,
+                         int precision, int32_t npol, hipStream_t s) {
+    if (P->n_pairs == 0) return hipSuccess;
+    if (precision == LR_F64) return expand_t<double>(P, Vg, vis, weight, npol, s);
+    return expand_t<float>(P, Vg, vis, weight, npol, s);
+}
+
+}  // namespace lr

@@ -1,0 +1,378 @@
+// Binning of (row, channel) pairs (the PreSolvePrep re-ordering): index map,
+// 64-bit sort keys, radix sort, grouping of identical samples and the
+// decomposition of the gridder's work into wavefront tasks.
+#include <string.h>
+
+#include <cstring>
+
+#include <rocprim/rocprim.hpp>
+
+#include "lr_internal.h"
+#include "lr_launch.h"
+
+namespace lr {
+
+// ---------------------------------------------------------------------------
+// Small host arrays reach the device through kernel arguments, so no host
+// buffer has to outlive an asynchronous copy.
+struct ChanUpload {
+    ChanConst c[kMaxChanPerUpload];
+    int32_t n, base;
+};
+
+__global__ void k_upload_chan(ChanUpload up, ChanConst *dst) {
+    int i = threadIdx.x;
+    if (i < up.n) dst[up.base + i] = up.c[i];
+}
+
+struct WordUpload {
+    uint32_t w[512];
+    int32_t n, base;
+};
+
+__global__ void k_upload_words(WordUpload up, uint32_t *dst) {
+    for (int i = threadIdx.x; i < up.n; i += blockDim.x) dst[up.base + i] = up.w[i];
+}
+
+hipError_t upload_chan(const std::vector<ChanConst> &cc, ChanConst *d, hipStream_t s) {
+    for (size_t b = 0; b < cc.size(); b += kMaxChanPerUpload) {
+        ChanUpload up;
+        up.n = (int32_t)std::min<size_t>(kMaxChanPerUpload, cc.size() - b);
+        up.base = (int32_t)b;
+        for (int i = 0; i < up.n; ++i) up.c[i] = cc[b + i];
+        hipLaunchKernelGGL(k_upload_chan, dim3(1), dim3(64), 0, s, up, d);
+    }
+    return hipGetLastError();
+}
+
+hipError_t upload_words(const void *src, size_t bytes, void *d, hipStream_t s) {
+    const uint32_t *w = (const uint32_t *)src;
+    size_t n = bytes / 4;
+    for (size_t b = 0; b < n; b += 512) {
+        WordUpload up;
+        up.n = (int32_t)std::min<size_t>(512, n - b);
+        up.base = (int32_t)b;
+        for (int i = 0; i < up.n; ++i) up.w[i] = w[b + i];
+        hipLaunchKernelGGL(k_upload_words, dim3(1), dim3(256), 0, s, up, (uint32_t *)d);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The channel constants travel by value, `up.n` channels from `up.base`.
+__global__ void k_debug_map(int64_t nrow, int32_t nchan, const double *uvw, ChanUpload up,
+                            MapGeom g, int32_t *out) {
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nrow * up.n) return;
+    int64_t r = j / up.n;
+    int32_t cl = (int32_t)(j - r * up.n);
+    int32_t c = up.base + cl;
+    int64_t i = r * nchan + c;
+    ChanConst ch = up.c[cl];
+    Map m = map_sample(uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], ch, g);
+    int32_t *o = out + 8 * i;
+    o[0] = m.pu; o[1] = m.pv; o[2] = m.ou; o[3] = m.ov;
+    o[4] = m.k; o[5] = m.conj; o[6] = m.keep; o[7] = ch.fg;
+}
+
+hipError_t launch_debug_map(int64_t nrow, int32_t nchan, const double *uvw,
+                            const std::vector<ChanConst> &cc, const MapGeom &g, int32_t *out,
+                            hipStream_t s) {
+    for (int32_t b = 0; b < nchan; b += kMaxChanPerUpload) {
+        ChanUpload up;
+        up.n = std::min<int32_t>(kMaxChanPerUpload, nchan - b);
+        up.base = b;
+        for (int i = 0; i < up.n; ++i) up.c[i] = cc[b + i];
+        int64_t n = nrow * up.n;
+        if (n == 0) continue;
+        hipLaunchKernelGGL(k_debug_map, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                           nrow, nchan, uvw, up, g, out);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Sort keys.  Fields from most to least significant: plane, A-term group,
+// w-plane, conj, p_v, p_u, [baseline, channel when a pointing phasor is
+// applied], o_v, o_u.  Keys of dropped or skipped pairs are all ones.
+__device__ __forceinline__ void put(unsigned __int128 &key, uint32_t v, int bits) {
+    if (bits) key = (key << bits) | (unsigned __int128)v;
+}
+
+__global__ void k_plan_keys(int64_t nrow, int32_t nchan, const double *uvw,
+                            const ChanConst *cc, MapGeom g, KeyLayout kl,
+                            const int32_t *ant1, const int32_t *ant2, int32_t nant,
+                            uint64_t *keys, int32_t *vals, unsigned long long *n_kept) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool kept = false;
+    if (i < nrow * nchan) {
+        int64_t r = i / nchan;
+        int32_t c = (int32_t)(i - r * nchan);
+        ChanConst ch = cc[c];
+        uint64_t key = ~0ull;
+        int32_t val = (int32_t)i;
+        if (ch.plane < 0) {
+            val |= (1 << 30);
+        } else {
+            Map m = map_sample(uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], ch, g);
+            if (m.keep) {
+                unsigned __int128 k128 = 0;
+                put(k128, (uint32_t)ch.plane, kl.b_plane);
+                put(k128, (uint32_t)ch.fg, kl.b_fg);
+                put(k128, (uint32_t)m.k, kl.b_k);
+                put(k128, (uint32_t)m.conj, kl.b_conj);
+                put(k128, (uint32_t)m.pv, kl.b_pv);
+                put(k128, (uint32_t)m.pu, kl.b_pu);
+                if (kl.b_bl) put(k128, (uint32_t)(ant1[r] * nant + ant2[r]), kl.b_bl);
+                if (kl.b_ch) put(k128, (uint32_t)c, kl.b_ch);
+                put(k128, (uint32_t)(m.ov + (g.O >> 1)), kl.b_o);
+                put(k128, (uint32_t)(m.ou + (g.O >> 1)), kl.b_o);
+                key = (uint64_t)(k128 >> kl.shift);
+                kept = true;
+            }
+        }
+        keys[i] = key;
+        vals[i] = val;
+    }
+    // one atomic per wavefront
+    unsigned long long b = __ballot(kept);
+    if ((threadIdx.x & 63) == 0 && b) atomicAdd(n_kept, (unsigned long long)__popcll(b));
+}
+
+__global__ void k_group_flags(const uint64_t *keys, int64_t n_kept, int32_t merged,
+                              int32_t *flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_kept) return;
+    flags[i] = (!merged || i == 0 || keys[i] != keys[i - 1]) ? 1 : 0;
+}
+
+__device__ __forceinline__ double airy_power(double x) {
+    if (x == 0.0) return 1.0;
+    double b = 2.0 * j1(x) / x;
+    return b * b;
+}
+
+__global__ void k_group_meta(const int32_t *vals, const int32_t *flags, const int32_t *gidx,
+                             int64_t n_kept, int32_t nchan, const double *uvw,
+                             const ChanConst *cc, MapGeom g, CFView cf,
+                             const int32_t *ant1, const int32_t *ant2,
+                             const double *ant_dlm, double du_dl, double dv_dm,
+                             int32_t *group_start, GroupMeta *groups) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_kept || !flags[i]) return;
+    int32_t gi = gidx[i];
+    group_start[gi] = (int32_t)i;
+    int32_t pair = vals[i] & ~(1 << 30);
+    int64_t r = pair / nchan;
+    int32_t c = pair - (int32_t)r * nchan;
+    ChanConst ch = cc[c];
+    Map m = map_sample(uvw[3 * r], uvw[3 * r + 1], uvw[3 * r + 2], ch, g);
+    GroupMeta gm;
+    int32_t h = g.h[m.k];
+    int64_t S = 2 * h + 1;
+    int64_t no = g.O + 1;
+    gm.cf_off = cf.plane_off[(int64_t)ch.fg * g.n_w + m.k] +
+                ((int64_t)(m.ov + (g.O >> 1)) * no + (m.ou + (g.O >> 1))) * S * S;
+    gm.cell = ((int64_t)ch.plane * g.npol) * (int64_t)g.ny * g.nx + (int64_t)m.pv * g.nx + m.pu;
+    gm.pu = m.pu;
+    gm.pv = m.pv;
+    gm.k = m.k;
+    gm.conj = m.conj;
+    gm.ou = m.ou;
+    gm.ov = m.ov;
+    gm.plane = ch.plane;
+    gm.fg = ch.fg;
+    gm.f = 1.0;
+    gm.bu = 0.0;
+    gm.bv = 0.0;
+    if (ant1) {
+        int32_t a1 = ant1[r], a2 = ant2[r];
+        double l1 = ant_dlm[2 * a1], m1 = ant_dlm[2 * a1 + 1];
+        double l2 = ant_dlm[2 * a2], m2 = ant_dlm[2 * a2 + 1];
+        double dl = 0.5 * (l1 + l2), dm = 0.5 * (m1 + m2);
+        double ddl = l1 - l2, ddm = m1 - m2;
+        double dist = sqrt(ddl * ddl + ddm * ddm);
+        gm.f = airy_power(ch.fscale * 0.5 * dist);
+        gm.bu = (du_dl * dl) / (double)g.O;
+        gm.bv = (dv_dm * dm) / (double)g.O;
+    }
+    groups[gi] = gm;
+}
+
+__global__ void k_group_end(int32_t *group_start, int64_t n_groups, int64_t n_kept) {
+    if (threadIdx.x == 0) group_start[n_groups] = (int32_t)n_kept;
+}
+
+// Ranges: runs of at most `per` groups of one w-plane.
+__global__ void k_range_flags(const GroupMeta *groups, int64_t n_groups, int32_t per,
+                              int32_t *flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_groups) return;
+    flags[i] = (i == 0 || (i % per) == 0 || groups[i].k != groups[i - 1].k) ? 1 : 0;
+}
+
+__global__ void k_range_build(const GroupMeta *groups, const int32_t *flags,
+                              const int32_t *ridx, int64_t n_groups, const int32_t *h,
+                              int32_t *r_g0, int32_t *r_nch) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_groups || !flags[i]) return;
+    int32_t r = ridx[i];
+    r_g0[r] = (int32_t)i;
+    int32_t S = 2 * h[groups[i].k] + 1;
+    r_nch[r] = (S * S + 63) / 64;
+}
+
+__global__ void k_taps(const GroupMeta *groups, int64_t n_groups, const int32_t *h,
+                       unsigned long long *out) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    unsigned long long t = 0;
+    if (i < n_groups) {
+        int64_t S = 2 * h[groups[i].k] + 1;
+        t = (unsigned long long)(S * S);
+    }
+    for (int off = 32; off > 0; off >>= 1) t += __shfl_xor(t, off);
+    if ((threadIdx.x & 63) == 0 && t) atomicAdd(out, t);
+}
+
+__global__ void k_range_end(int32_t *r_g0, int32_t *r_toff, const int32_t *r_nch,
+                            int64_t n_ranges, int64_t n_groups) {
+    if (threadIdx.x == 0) {
+        r_g0[n_ranges] = (int32_t)n_groups;
+        r_toff[n_ranges] = r_toff[n_ranges - 1] + r_nch[n_ranges - 1];
+    }
+}
+
+// ---------------------------------------------------------------------------
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+size_t sort_temp_bytes(int64_t n) {
+    size_t bytes = 0;
+    rocprim::radix_sort_pairs((void *)nullptr, bytes, (uint64_t *)nullptr,
+                              (uint64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
+                              (size_t)n, 0, 64);
+    size_t sb = 0;
+    rocprim::exclusive_scan((void *)nullptr, sb, (int32_t *)nullptr, (int32_t *)nullptr,
+                            (int32_t)0, (size_t)n, rocprim::plus<int32_t>());
+    return std::max(bytes, sb);
+}
+
+PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t per, int64_t n_segments) {
+    PlanLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
+    int64_t n = std::max<int64_t>(n_pairs, 1);
+    L.chan = take(sizeof(ChanConst) * (nchan > 0 ? nchan : 1));
+    // ranges: one per `per` groups plus one per change of w-plane in the
+    // sorted order (at most one per (plane, A-term group, w-plane) segment)
+    int64_t nr = n / per + n_segments + 2;
+    L.order = take(sizeof(int32_t) * n);
+    L.gidx = take(sizeof(int32_t) * n);
+    L.group_start = take(sizeof(int32_t) * (n + 1));
+    L.groups = take(sizeof(GroupMeta) * n);
+    L.r_g0 = take(sizeof(int32_t) * (nr + 1));
+    L.r_toff = take(sizeof(int32_t) * (nr + 1));
+    L.persistent = off;
+    // transient
+    L.keys_a = take(sizeof(uint64_t) * n);
+    L.keys_b = take(sizeof(uint64_t) * n);
+    L.vals_a = take(sizeof(int32_t) * n);
+    L.flags = take(sizeof(int32_t) * n);
+    L.r_nch = take(sizeof(int32_t) * (nr + 1));
+    L.counter = take(64);
+    L.temp = take(sort_temp_bytes(n));
+    L.max_ranges = nr;
+    L.total = off;
+    return L;
+}
+
+static inline unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const double *uvw,
+                             const ChanConst *d_cc, const MapGeom &g, const KeyLayout &kl,
+                             const CFView &cf, const int32_t *ant1, const int32_t *ant2,
+                             int32_t nant, const double *ant_dlm, double du_dl,
+                             double dv_dm, int32_t per, hipStream_t s) {
+    hipError_t e;
+    int64_t n = P->n_pairs;
+    uint64_t *keys_a = (uint64_t *)(buf + L.keys_a), *keys_b = (uint64_t *)(buf + L.keys_b);
+    int32_t *vals_a = (int32_t *)(buf + L.vals_a);
+    int32_t *order = (int32_t *)(buf + L.order);
+    int32_t *flags = (int32_t *)(buf + L.flags);
+    int32_t *gidx = (int32_t *)(buf + L.gidx);
+    unsigned long long *counter = (unsigned long long *)(buf + L.counter);
+    void *temp = buf + L.temp;
+    size_t temp_bytes = sort_temp_bytes(n);
+    P->order = order;
+    P->gidx = gidx;
+    P->group_start = (int32_t *)(buf + L.group_start);
+    P->groups = (GroupMeta *)(buf + L.groups);
+    P->r_g0 = (int32_t *)(buf + L.r_g0);
+    P->r_toff = (int32_t *)(buf + L.r_toff);
+    P->n_kept = P->n_groups = P->n_ranges = P->n_tasks = 0;
+    if (n == 0) return hipSuccess;
+
+    if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_plan_keys, dim3(blocks(n, 256)), dim3(256), 0, s, P->nrow, P->nchan,
+                       uvw, d_cc, g, kl, ant1, ant2, nant, keys_a, vals_a, counter);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    e = rocprim::radix_sort_pairs(temp, temp_bytes, keys_a, keys_b, vals_a, order, (size_t)n,
+                                  0, kl.end_bit, s);
+    if (e != hipSuccess) return e;
+    unsigned long long nk = 0;
+    if ((e = hipMemcpyAsync(&nk, counter, sizeof nk, hipMemcpyDeviceToHost, s)) != hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    P->n_kept = (int64_t)nk;
+    if (nk == 0) return hipSuccess;
+
+    hipLaunchKernelGGL(k_group_flags, dim3(blocks(nk, 256)), dim3(256), 0, s, keys_b,
+                       (int64_t)nk, P->merged, flags);
+    e = rocprim::exclusive_scan(temp, temp_bytes, flags, gidx, (int32_t)0, (size_t)nk,
+                                rocprim::plus<int32_t>(), s);
+    if (e != hipSuccess) return e;
+    int32_t tail[2] = {0, 0};
+    (void)hipMemcpyAsync(&tail[0], gidx + nk - 1, 4, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&tail[1], flags + nk - 1, 4, hipMemcpyDeviceToHost, s);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    P->n_groups = (int64_t)tail[0] + tail[1];
+    hipLaunchKernelGGL(k_group_meta, dim3(blocks(nk, 256)), dim3(256), 0, s, order, flags,
+                       gidx, (int64_t)nk, P->nchan, uvw, d_cc, g, cf, ant1, ant2, ant_dlm,
+                       du_dl, dv_dm, P->group_start, P->groups);
+    hipLaunchKernelGGL(k_group_end, dim3(1), dim3(64), 0, s, P->group_start, P->n_groups,
+                       (int64_t)nk);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+
+    // wavefront tasks of the gridder
+    int32_t *r_nch = (int32_t *)(buf + L.r_nch);
+    hipLaunchKernelGGL(k_range_flags, dim3(blocks(P->n_groups, 256)), dim3(256), 0, s,
+                       P->groups, P->n_groups, per, flags);
+    e = rocprim::exclusive_scan(temp, temp_bytes, flags, (int32_t *)keys_a, (int32_t)0,
+                                (size_t)P->n_groups, rocprim::plus<int32_t>(), s);
+    if (e != hipSuccess) return e;
+    int32_t *ridx = (int32_t *)keys_a;
+    (void)hipMemcpyAsync(&tail[0], ridx + P->n_groups - 1, 4, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&tail[1], flags + P->n_groups - 1, 4, hipMemcpyDeviceToHost, s);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    P->n_ranges = (int64_t)tail[0] + tail[1];
+    if (P->n_ranges > L.max_ranges) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_range_build, dim3(blocks(P->n_groups, 256)), dim3(256), 0, s,
+                       P->groups, flags, ridx, P->n_groups, cf.h, P->r_g0, r_nch);
+    e = rocprim::exclusive_scan(temp, temp_bytes, r_nch, P->r_toff, (int32_t)0,
+                                (size_t)P->n_ranges, rocprim::plus<int32_t>(), s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_range_end, dim3(1), dim3(64), 0, s, P->r_g0, P->r_toff, r_nch,
+                       P->n_ranges, P->n_groups);
+    if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_taps, dim3(blocks(P->n_groups, 256)), dim3(256), 0, s, P->groups,
+                       P->n_groups, cf.h, counter);
+    int32_t nt = 0;
+    unsigned long long taps = 0;
+    (void)hipMemcpyAsync(&nt, P->r_toff + P->n_ranges, 4, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&taps, counter, 8, hipMemcpyDeviceToHost, s);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    P->n_tasks = nt;
+    P->taps = (int64_t)taps;
+    return hipGetLastError();
+}
+
+}  // namespace lr

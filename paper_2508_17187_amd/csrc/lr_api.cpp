@@ -1,0 +1,643 @@
+// C ABI of the gfx950 gridding library: validation, derived geometry,
+// workspace carving and dispatch to the kernels.  All host arithmetic that
+// feeds the bit-exact index map is FP64 without contraction (this file is
+// compiled with -ffp-contract=off).
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "lr_internal.h"
+#include "lr_launch.h"
+
+using namespace lr;
+
+namespace {
+
+thread_local std::string g_err;
+thread_local hipEvent_t g_prof_start = nullptr, g_prof_stop = nullptr;
+
+// Record the pending profile events around the main kernel of a call.
+struct ProfileScope {
+    hipStream_t s;
+    hipEvent_t a, b;
+    explicit ProfileScope(hipStream_t st) : s(st), a(g_prof_start), b(g_prof_stop) {
+        g_prof_start = g_prof_stop = nullptr;
+    }
+    void begin() { if (a) (void)hipEventRecord(a, s); }
+    void end() { if (b) (void)hipEventRecord(b, s); }
+};
+
+lr_status fail(lr_status s, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+lr_status dev_fail(hipError_t e, const char *what) {
+    return fail(LR_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int bitwidth(int64_t maxval) {
+    int b = 0;
+    while (maxval > 0) { ++b; maxval >>= 1; }
+    return b;
+}
+
+std::vector<int32_t> half_widths(int32_t n_w, int32_t h_min, int32_t h_max) {
+    std::vector<int32_t> h(n_w);
+    if (n_w == 1) { h[0] = h_min; return h; }
+    for (int64_t k = 0; k < n_w; ++k)
+        h[k] = (int32_t)(h_min + (2 * (int64_t)(h_max - h_min) * k + n_w - 1) / (2 * (int64_t)(n_w - 1)));
+    return h;
+}
+
+size_t elem_bytes_of(lr_precision p) {
+    switch (p) {
+        case LR_F64: return 16;
+        case LR_F32: return 8;
+        case LR_F32_CF16:
+        case LR_F32_CFBF16: return 4;
+    }
+    return 0;
+}
+
+lr_status check_grid(const lr_grid_spec *g) {
+    if (!g) return fail(LR_E_ARG, "grid spec is NULL");
+    if (g->nx < 8 || g->ny < 8 || (g->nx & 1) || (g->ny & 1))
+        return fail(LR_E_ARG, "nx, ny must be even and >= 8 (got %d x %d)", g->nx, g->ny);
+    if (g->nx > 16384 || g->ny > 16384) return fail(LR_E_RANGE, "nx, ny must be <= 16384");
+    if (!(g->npol == 1 || g->npol == 2 || g->npol == 4))
+        return fail(LR_E_ARG, "npol must be 1, 2 or 4 (got %d)", g->npol);
+    if (g->nplane < 1 || g->nplane > 4096) return fail(LR_E_ARG, "nplane must be in 1..4096");
+    if (!(g->cell_l > 0.0) || !(g->cell_m > 0.0) || !std::isfinite(g->cell_l) ||
+        !std::isfinite(g->cell_m))
+        return fail(LR_E_ARG, "cell sizes must be positive and finite");
+    return LR_OK;
+}
+
+lr_status check_spec(const lr_cf_spec *s) {
+    if (!s) return fail(LR_E_ARG, "cf spec is NULL");
+    if (s->terms == 0 || (s->terms & ~7u)) return fail(LR_E_ARG, "terms must be a nonzero set of PS|W|A");
+    if (s->oversample < 2 || s->oversample > 126 || (s->oversample & 1))
+        return fail(LR_E_ARG, "oversample must be even in 2..126 (got %d)", s->oversample);
+    if (s->n_w < 1 || s->n_w > 255) return fail(LR_E_ARG, "n_w must be in 1..255");
+    if (s->n_w > 1 && !(s->w_max > 0.0 && std::isfinite(s->w_max)))
+        return fail(LR_E_ARG, "w_max must be positive when n_w > 1");
+    if (s->h_min < 0 || s->h_max < s->h_min || s->h_max > 128)
+        return fail(LR_E_ARG, "need 0 <= h_min <= h_max <= 128");
+    if (s->n_w == 1 && s->h_min != s->h_max)
+        return fail(LR_E_ARG, "a single w-plane needs h_min == h_max");
+    if (s->n_fg < 1 || s->n_fg > 127) return fail(LR_E_ARG, "n_fg must be in 1..127");
+    if (!s->fg_hz) return fail(LR_E_ARG, "fg_hz is NULL");
+    for (int i = 0; i < s->n_fg; ++i)
+        if (!(s->fg_hz[i] > 0.0) || !std::isfinite(s->fg_hz[i]))
+            return fail(LR_E_ARG, "fg_hz[%d] must be positive", i);
+    if ((s->terms & LR_TERM_PS) && (s->ps_support < 1 || s->ps_support > 64))
+        return fail(LR_E_ARG, "ps_support must be in 1..64");
+    if ((s->terms & LR_TERM_A) && !(s->dish_m > 0.0)) return fail(LR_E_ARG, "dish_m must be positive");
+    if (s->screen_m < 0 || (s->screen_m & 1)) return fail(LR_E_ARG, "screen_m must be even (0 = auto)");
+    if (elem_bytes_of(s->storage) == 0) return fail(LR_E_DTYPE, "unknown storage type");
+    return LR_OK;
+}
+
+struct Geometry {
+    std::vector<int32_t> h;
+    int32_t M = 0, hmax = 0;
+    std::vector<int64_t> plane_off;
+    int64_t n_elems = 0;
+    size_t off_h = 0, off_po = 0, off_exp = 0, off_scale = 0, off_table = 0, total = 0;
+};
+
+lr_status geometry(const lr_cf_spec *s, const lr_grid_spec *g, Geometry &G) {
+    lr_status st;
+    if ((st = check_spec(s)) != LR_OK) return st;
+    if ((st = check_grid(g)) != LR_OK) return st;
+    G.h = half_widths(s->n_w, s->h_min, s->h_max);
+    G.hmax = *std::max_element(G.h.begin(), G.h.end());
+    int32_t smax = 2 * G.hmax + 1;
+    G.M = s->screen_m ? s->screen_m : 2 * smax;
+    if (G.M <= smax) return fail(LR_E_ARG, "screen_m must exceed the largest support");
+    if ((int64_t)G.M > 4096) return fail(LR_E_RANGE, "screen size M must be <= 4096");
+    if ((int64_t)s->oversample * G.M > (1 << 20)) return fail(LR_E_RANGE, "O*M too large");
+    int64_t no = s->oversample + 1;
+    int np = s->n_fg * s->n_w;
+    G.plane_off.resize(np);
+    int64_t acc = 0;
+    for (int f = 0; f < s->n_fg; ++f)
+        for (int k = 0; k < s->n_w; ++k) {
+            G.plane_off[f * s->n_w + k] = acc;
+            int64_t S = 2 * G.h[k] + 1;
+            acc += no * no * S * S;
+        }
+    G.n_elems = acc;
+    size_t eb = elem_bytes_of(s->storage);
+    G.off_h = 0;
+    G.off_po = al256(sizeof(int32_t) * s->n_w);
+    G.off_exp = G.off_po + al256(sizeof(int64_t) * np);
+    G.off_scale = G.off_exp + al256(sizeof(int32_t) * np);
+    G.off_table = G.off_scale + al256(sizeof(float) * np);
+    G.total = G.off_table + (size_t)G.n_elems * eb;
+    return LR_OK;
+}
+
+CFView view_of(const lr_cf *cf) {
+    CFView v;
+    v.table = cf->d_table;
+    v.plane_off = cf->d_plane_off;
+    v.scale = cf->d_scale;
+    v.h = cf->d_h;
+    v.O = cf->spec.oversample;
+    v.n_w = cf->spec.n_w;
+    v.n_fg = cf->spec.n_fg;
+    v.storage = cf->spec.storage;
+    return v;
+}
+
+lr_cf *make_handle(const lr_cf_spec *s, const lr_grid_spec *g, const Geometry &G, void *buf) {
+    lr_cf *cf = new (std::nothrow) lr_cf;
+    if (!cf) return nullptr;
+    cf->spec = *s;
+    cf->fg_hz.assign(s->fg_hz, s->fg_hz + s->n_fg);
+    cf->spec.fg_hz = cf->fg_hz.data();
+    cf->grid = *g;
+    cf->M = G.M;
+    cf->h = G.h;
+    cf->plane_off = G.plane_off;
+    cf->n_elems = G.n_elems;
+    cf->elem_bytes = elem_bytes_of(s->storage);
+    cf->header_bytes = G.off_table;
+    cf->total_bytes = G.total;
+    cf->blob = (char *)buf;
+    cf->d_h = (int32_t *)(cf->blob + G.off_h);
+    cf->d_plane_off = (int64_t *)(cf->blob + G.off_po);
+    cf->d_exp = (int32_t *)(cf->blob + G.off_exp);
+    cf->d_scale = (float *)(cf->blob + G.off_scale);
+    cf->d_table = cf->blob + G.off_table;
+    return cf;
+}
+
+// ---- visibility descriptors ----------------------------------------------------
+lr_status check_vis(const lr_cf *cf, const lr_vis *v, bool need_vis, bool need_weight) {
+    if (!cf) return fail(LR_E_ARG, "cf handle is NULL");
+    if (!v) return fail(LR_E_ARG, "vis descriptor is NULL");
+    if (v->nrow < 0) return fail(LR_E_ARG, "nrow must be >= 0");
+    if (v->nchan < 1) return fail(LR_E_ARG, "nchan must be >= 1");
+    if (v->npol != cf->grid.npol) return fail(LR_E_ARG, "vis npol %d != grid npol %d", v->npol, cf->grid.npol);
+    if ((int64_t)v->nrow * v->nchan >= (1ll << 30))
+        return fail(LR_E_RANGE, "nrow * nchan must be < 2^30 per call (stream larger data in chunks)");
+    if (v->nrow > 0 && !v->uvw) return fail(LR_E_ARG, "uvw is NULL");
+    if (!v->freq_hz || !v->chan_plane) return fail(LR_E_ARG, "freq_hz and chan_plane are required");
+    for (int c = 0; c < v->nchan; ++c) {
+        if (!(v->freq_hz[c] > 0.0) || !std::isfinite(v->freq_hz[c]))
+            return fail(LR_E_ARG, "freq_hz[%d] must be positive", c);
+        if (v->chan_plane[c] >= cf->grid.nplane)
+            return fail(LR_E_ARG, "chan_plane[%d] = %d >= nplane", c, v->chan_plane[c]);
+        int fg = v->chan_fg ? v->chan_fg[c] : 0;
+        if (fg < 0 || fg >= cf->spec.n_fg) return fail(LR_E_ARG, "chan_fg[%d] out of range", c);
+    }
+    if (need_vis && v->nrow > 0 && !v->vis) return fail(LR_E_ARG, "vis is NULL");
+    if (need_weight && v->nrow > 0 && !v->weight) return fail(LR_E_ARG, "weight is NULL");
+    bool po = v->ant1 || v->ant2 || v->ant_dlm;
+    if (po && !(v->ant1 && v->ant2 && v->ant_dlm && v->nant > 0))
+        return fail(LR_E_ARG, "pointing phasor needs ant1, ant2, ant_dlm and nant > 0");
+    if (po && (int64_t)v->nant * v->nant > (1 << 24)) return fail(LR_E_RANGE, "nant too large");
+    return LR_OK;
+}
+
+lr_status check_precision(const lr_cf *cf, lr_precision p) {
+    if (elem_bytes_of(p) == 0) return fail(LR_E_DTYPE, "unknown precision %d", (int)p);
+    if (cf->spec.storage != p)
+        return fail(LR_E_DTYPE, "CF storage %d does not match precision %d",
+                    (int)cf->spec.storage, (int)p);
+    return LR_OK;
+}
+
+std::vector<ChanConst> chan_consts(const lr_cf *cf, const lr_vis *v) {
+    std::vector<ChanConst> cc(v->nchan);
+    const lr_grid_spec &g = cf->grid;
+    const lr_cf_spec &s = cf->spec;
+    for (int c = 0; c < v->nchan; ++c) {
+        double sc = v->freq_hz[c] / kCLight;
+        cc[c].kx = ((sc * (double)g.nx) * g.cell_l) * (double)s.oversample;
+        cc[c].ky = ((sc * (double)g.ny) * g.cell_m) * (double)s.oversample;
+        cc[c].kw = s.n_w > 1 ? sc * ((double)(s.n_w - 1) / s.w_max) : 0.0;
+        cc[c].fscale = ((M_PI * s.dish_m) * v->freq_hz[c]) / kCLight;
+        cc[c].plane = v->chan_plane[c];
+        cc[c].fg = v->chan_fg ? v->chan_fg[c] : 0;
+        cc[c].pad0 = cc[c].pad1 = 0;
+    }
+    return cc;
+}
+
+MapGeom map_geom(const lr_cf *cf, int32_t nchan, int psf) {
+    MapGeom m;
+    const lr_grid_spec &g = cf->grid;
+    m.nx = g.nx;
+    m.ny = g.ny;
+    m.O = cf->spec.oversample;
+    m.n_w = cf->spec.n_w;
+    m.psf = psf;
+    m.npol = g.npol;
+    m.nplane = g.nplane;
+    m.nchan = nchan;
+    m.ox = (double)(g.nx / 2) * (double)m.O + 0.5;
+    m.oy = (double)(g.ny / 2) * (double)m.O + 0.5;
+    m.limx = (double)g.nx * (double)m.O;
+    m.limy = (double)g.ny * (double)m.O;
+    m.h = cf->d_h;
+    return m;
+}
+
+int32_t range_groups() {
+    static int32_t v = [] {
+        const char *e = getenv("LR_GRID_RANGE");
+        int x = e ? atoi(e) : 0;
+        return x >= 1 && x <= (1 << 20) ? x : 128;
+    }();
+    return v;
+}
+
+KeyLayout key_layout(const lr_cf *cf, const lr_vis *v, bool po, int32_t &merged) {
+    KeyLayout k;
+    const lr_grid_spec &g = cf->grid;
+    k.b_plane = bitwidth(g.nplane - 1);
+    k.b_fg = bitwidth(cf->spec.n_fg - 1);
+    k.b_k = bitwidth(cf->spec.n_w - 1);
+    k.b_conj = cf->spec.n_w > 1 ? 1 : 0;
+    k.b_pv = bitwidth(g.ny - 1);
+    k.b_pu = bitwidth(g.nx - 1);
+    k.b_bl = po ? bitwidth((int64_t)v->nant * v->nant - 1) : 0;
+    k.b_ch = po ? bitwidth(v->nchan - 1) : 0;
+    k.b_o = bitwidth(cf->spec.oversample - 1);
+    int total = k.b_plane + k.b_fg + k.b_k + k.b_conj + k.b_pv + k.b_pu + k.b_bl + k.b_ch + 2 * k.b_o;
+    if (total <= 63) {
+        k.shift = 0;
+        k.end_bit = total + 1;
+        merged = 1;
+    } else {
+        k.shift = total - 63;
+        k.end_bit = 64;
+        merged = 0;
+    }
+    return k;
+}
+
+int64_t n_segments(const lr_cf *cf) {
+    return (int64_t)cf->grid.nplane * cf->spec.n_fg * cf->spec.n_w;
+}
+
+size_t plan_total(const lr_cf *cf, const lr_vis *v) {
+    return plan_layout((int64_t)v->nrow * v->nchan, v->nchan, range_groups(), n_segments(cf)).total;
+}
+
+lr_status plan_matches(const lr_plan *P, const lr_cf *cf, const lr_vis *v, int psf) {
+    if (P->cf != cf) return fail(LR_E_ARG, "plan was built for another CF handle");
+    if (P->nrow != v->nrow || P->nchan != v->nchan || P->npol != v->npol)
+        return fail(LR_E_ARG, "plan was built for other data dimensions");
+    if (P->psf != psf) return fail(LR_E_ARG, "plan footprint rule (psf=%d) does not match the call", P->psf);
+    bool po = v->ant1 != nullptr;
+    if ((P->po != 0) != po) return fail(LR_E_ARG, "plan pointing-phasor setting does not match the call");
+    for (int c = 0; c < v->nchan; ++c) {
+        int fg = v->chan_fg ? v->chan_fg[c] : 0;
+        if (P->freq[c] != v->freq_hz[c] || P->chan_plane[c] != v->chan_plane[c] ||
+            P->chan_fg[c] != fg)
+            return fail(LR_E_ARG, "plan was built for other channel settings");
+    }
+    return LR_OK;
+}
+
+// Build a plan into `buf` (caller memory).  Synchronises the stream.
+lr_status build_plan(const lr_cf *cf, const lr_vis *v, int psf, void *buf, size_t bytes,
+                     hipStream_t s, lr_plan *P) {
+    int64_t n_pairs = (int64_t)v->nrow * v->nchan;
+    PlanLayout L = plan_layout(n_pairs, v->nchan, range_groups(), n_segments(cf));
+    if (!buf && L.total) return fail(LR_E_ARG, "plan buffer is NULL");
+    if (bytes < L.total) return fail(LR_E_WORKSPACE, "plan needs %zu bytes, got %zu", L.total, bytes);
+    bool po = v->ant1 != nullptr;
+    P->cf = cf;
+    P->nrow = v->nrow;
+    P->nchan = v->nchan;
+    P->npol = v->npol;
+    P->psf = psf;
+    P->po = po ? 1 : 0;
+    P->freq.assign(v->freq_hz, v->freq_hz + v->nchan);
+    P->chan_plane.assign(v->chan_plane, v->chan_plane + v->nchan);
+    P->chan_fg.resize(v->nchan);
+    for (int c = 0; c < v->nchan; ++c) P->chan_fg[c] = v->chan_fg ? v->chan_fg[c] : 0;
+    P->n_pairs = n_pairs;
+    P->bytes_used = L.total;
+    KeyLayout kl = key_layout(cf, v, po, P->merged);
+    char *b = (char *)buf;
+    std::vector<ChanConst> cc = chan_consts(cf, v);
+    ChanConst *d_cc = (ChanConst *)(b + L.chan);
+    hipError_t e = upload_chan(cc, d_cc, s);
+    if (e != hipSuccess) return dev_fail(e, "channel upload");
+    MapGeom g = map_geom(cf, v->nchan, psf);
+    double du_dl = 1.0 / ((double)cf->grid.nx * cf->grid.cell_l);
+    double dv_dm = 1.0 / ((double)cf->grid.ny * cf->grid.cell_m);
+    e = build_plan_device(P, b, L, v->uvw, d_cc, g, kl, view_of(cf), v->ant1, v->ant2,
+                          v->nant, v->ant_dlm, du_dl, dv_dm, range_groups(), s);
+    if (e == hipErrorInvalidValue && P->n_ranges > L.max_ranges)
+        return fail(LR_E_RANGE, "plan range table overflow");
+    if (e != hipSuccess) return dev_fail(e, "plan build");
+    return LR_OK;
+}
+
+// Resolve the plan of a call: the caller's, or a transient one at the start
+// of the workspace.  Returns the workspace bytes it used.
+lr_status resolve_plan(const lr_cf *cf, const lr_vis *v, int psf, void *work,
+                       size_t work_bytes, hipStream_t s, lr_plan &tmp, const lr_plan *&P,
+                       size_t &used) {
+    if (v->plan) {
+        lr_status st = plan_matches(v->plan, cf, v, psf);
+        if (st != LR_OK) return st;
+        P = v->plan;
+        used = 0;
+        return LR_OK;
+    }
+    size_t need = plan_total(cf, v);
+    if (work_bytes < need) return fail(LR_E_WORKSPACE, "workspace needs %zu bytes for a transient plan, got %zu", need, work_bytes);
+    lr_status st = build_plan(cf, v, psf, work, work_bytes, s, &tmp);
+    if (st != LR_OK) return st;
+    P = &tmp;
+    used = al256(need);
+    return LR_OK;
+}
+
+size_t cplx_bytes(lr_precision p) { return p == LR_F64 ? 16 : 8; }
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+const char *lr_status_str(lr_status s) {
+    switch (s) {
+        case LR_OK: return "LR_OK";
+        case LR_E_ARG: return "LR_E_ARG";
+        case LR_E_DTYPE: return "LR_E_DTYPE";
+        case LR_E_WORKSPACE: return "LR_E_WORKSPACE";
+        case LR_E_CF: return "LR_E_CF";
+        case LR_E_DEVICE: return "LR_E_DEVICE";
+        case LR_E_RANGE: return "LR_E_RANGE";
+    }
+    return "LR_E_UNKNOWN";
+}
+
+const char *lr_last_error(void) { return g_err.c_str(); }
+
+size_t lr_cf_bytes(const lr_cf_spec *spec, const lr_grid_spec *grid) {
+    Geometry G;
+    if (geometry(spec, grid, G) != LR_OK) return 0;
+    return G.total;
+}
+
+size_t lr_workspace_bytes(int op, const lr_cf_spec *spec, const lr_grid_spec *grid,
+                          const lr_vis *vis, lr_precision precision) {
+    Geometry G;
+    if (geometry(spec, grid, G) != LR_OK) return 0;
+    if (op == LR_OP_CF_BUILD) return cf_work_bytes(G.M, spec->oversample, G.hmax);
+    if (!vis) { fail(LR_E_ARG, "vis descriptor is NULL"); return 0; }
+    int64_t n_pairs = (int64_t)vis->nrow * vis->nchan;
+    int64_t n_segs = (int64_t)grid->nplane * spec->n_fg * spec->n_w;
+    size_t plan = vis->plan ? 0 : al256(plan_layout(n_pairs, vis->nchan, range_groups(), n_segs).total);
+    int64_t n_groups = vis->plan ? vis->plan->n_groups : n_pairs;
+    size_t per = 0;
+    if (op == LR_OP_GRID || op == LR_OP_PSF || op == LR_OP_DEGRID)
+        per = al256((size_t)std::max<int64_t>(n_groups, 1) * grid->npol * cplx_bytes(precision));
+    return plan + per + 256;
+}
+
+lr_status lr_cf_build(const lr_cf_spec *spec, const lr_grid_spec *grid, void *cf_buf,
+                      size_t cf_bytes, void *work, size_t work_bytes, lr_stream stream,
+                      lr_cf **out) {
+    if (!out) return fail(LR_E_ARG, "out is NULL");
+    *out = nullptr;
+    Geometry G;
+    lr_status st = geometry(spec, grid, G);
+    if (st != LR_OK) return st;
+    if (!cf_buf) return fail(LR_E_ARG, "cf_buf is NULL");
+    if (cf_bytes < G.total) return fail(LR_E_WORKSPACE, "CF blob needs %zu bytes, got %zu", G.total, cf_bytes);
+    size_t wneed = cf_work_bytes(G.M, spec->oversample, G.hmax);
+    if (!work || work_bytes < wneed)
+        return fail(LR_E_WORKSPACE, "CF build needs %zu bytes of workspace, got %zu", wneed, work_bytes);
+    lr_cf *cf = make_handle(spec, grid, G, cf_buf);
+    if (!cf) return fail(LR_E_ARG, "out of host memory");
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = upload_words(G.h.data(), sizeof(int32_t) * G.h.size(), cf->d_h, s);
+    if (e == hipSuccess)
+        e = upload_words(G.plane_off.data(), sizeof(int64_t) * G.plane_off.size(),
+                         cf->d_plane_off, s);
+    if (e != hipSuccess) { delete cf; return dev_fail(e, "CF header upload"); }
+    CFBuildArgs a;
+    a.M = G.M;
+    a.O = spec->oversample;
+    a.nx = grid->nx;
+    a.ny = grid->ny;
+    a.terms = (int32_t)spec->terms;
+    a.cell_l = grid->cell_l;
+    a.cell_m = grid->cell_m;
+    a.c_ps = M_PI * spec->ps_support / 2.0;
+    a.dish_m = spec->dish_m;
+    e = launch_cf_build(cf, a, work, s);
+    if (e != hipSuccess) { delete cf; return dev_fail(e, "CF build"); }
+    *out = cf;
+    return LR_OK;
+}
+
+lr_status lr_cf_attach(const lr_cf_spec *spec, const lr_grid_spec *grid, void *cf_buf,
+                       size_t cf_bytes, lr_cf **out) {
+    if (!out) return fail(LR_E_ARG, "out is NULL");
+    *out = nullptr;
+    Geometry G;
+    lr_status st = geometry(spec, grid, G);
+    if (st != LR_OK) return st;
+    if (!cf_buf) return fail(LR_E_ARG, "cf_buf is NULL");
+    if (cf_bytes < G.total) return fail(LR_E_CF, "CF blob has %zu bytes, the spec needs %zu", cf_bytes, G.total);
+    lr_cf *cf = make_handle(spec, grid, G, cf_buf);
+    if (!cf) return fail(LR_E_ARG, "out of host memory");
+    *out = cf;
+    return LR_OK;
+}
+
+void lr_cf_free(lr_cf *cf) { delete cf; }
+
+lr_status lr_cf_scale_exponents(const lr_cf *cf, int32_t *exps, lr_stream stream) {
+    if (!cf || !exps) return fail(LR_E_ARG, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    size_t n = (size_t)cf->spec.n_fg * cf->spec.n_w;
+    hipError_t e = hipMemcpyAsync(exps, cf->d_exp, n * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return dev_fail(e, "read scale exponents");
+    return LR_OK;
+}
+
+lr_status lr_cf_layout(const lr_cf *cf, size_t *table_offset, size_t *elem_bytes,
+                       int64_t *n_elems, int64_t *plane_off) {
+    if (!cf) return fail(LR_E_ARG, "cf handle is NULL");
+    if (table_offset) *table_offset = cf->header_bytes;
+    if (elem_bytes) *elem_bytes = cf->elem_bytes;
+    if (n_elems) *n_elems = cf->n_elems;
+    if (plane_off) std::copy(cf->plane_off.begin(), cf->plane_off.end(), plane_off);
+    return LR_OK;
+}
+
+size_t lr_plan_bytes(const lr_cf *cf, const lr_vis *vis, int psf) {
+    (void)psf;
+    if (check_vis(cf, vis, false, false) != LR_OK) return 0;
+    return plan_total(cf, vis);
+}
+
+lr_status lr_plan_build(const lr_cf *cf, const lr_vis *vis, int psf, void *buf, size_t bytes,
+                        lr_stream stream, lr_plan **out) {
+    if (!out) return fail(LR_E_ARG, "out is NULL");
+    *out = nullptr;
+    lr_status st = check_vis(cf, vis, false, false);
+    if (st != LR_OK) return st;
+    lr_plan *P = new (std::nothrow) lr_plan;
+    if (!P) return fail(LR_E_ARG, "out of host memory");
+    st = build_plan(cf, vis, psf ? 1 : 0, buf, bytes, (hipStream_t)stream, P);
+    if (st != LR_OK) { delete P; return st; }
+    *out = P;
+    return LR_OK;
+}
+
+void lr_plan_free(lr_plan *plan) { delete plan; }
+
+lr_status lr_plan_info(const lr_plan *plan, int64_t *n_groups, int64_t *n_kept,
+                       int64_t *n_pairs, int64_t *taps) {
+    if (!plan) return fail(LR_E_ARG, "plan is NULL");
+    if (n_groups) *n_groups = plan->n_groups;
+    if (n_kept) *n_kept = plan->n_kept;
+    if (n_pairs) *n_pairs = plan->n_pairs;
+    if (taps) *taps = plan->taps;
+    return LR_OK;
+}
+
+lr_status lr_set_profile_events(void *start, void *stop) {
+    if ((start == nullptr) != (stop == nullptr))
+        return fail(LR_E_ARG, "give both events or neither");
+    g_prof_start = (hipEvent_t)start;
+    g_prof_stop = (hipEvent_t)stop;
+    return LR_OK;
+}
+
+static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
+                             void *grid, double *sumwt, int64_t *counters, void *work,
+                             size_t work_bytes, lr_stream stream, int psf) {
+    lr_status st = check_vis(cf, vis, !psf, true);
+    if (st != LR_OK) return st;
+    if ((st = check_precision(cf, precision)) != LR_OK) return st;
+    if (!grid) return fail(LR_E_ARG, "grid is NULL");
+    if (!work && work_bytes) return fail(LR_E_ARG, "work is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    // size check of the per-call scratch before anything is enqueued
+    int64_t ng_bound = vis->plan ? vis->plan->n_groups : (int64_t)vis->nrow * vis->nchan;
+    size_t a_bytes = al256((size_t)std::max<int64_t>(ng_bound, 1) * vis->npol * cplx_bytes(precision));
+    size_t plan_need = vis->plan ? 0 : al256(plan_total(cf, vis));
+    if (work_bytes < plan_need + a_bytes)
+        return fail(LR_E_WORKSPACE, "workspace needs %zu bytes, got %zu", plan_need + a_bytes, work_bytes);
+    lr_plan tmp;
+    const lr_plan *P = nullptr;
+    size_t used = 0;
+    if ((st = resolve_plan(cf, vis, psf, work, work_bytes, s, tmp, P, used)) != LR_OK) return st;
+    void *A = (char *)work + used;
+    VisArgs va{vis->vis, vis->weight, vis->npol, psf ? 1 : 0};
+    ProfileScope prof(s);
+    hipError_t e = launch_presum(P, va, precision, A, sumwt, counters, cf->grid.nplane, s);
+    if (e == hipSuccess) {
+        prof.begin();
+        e = launch_grid(P, view_of(cf), A, grid, precision, vis->npol, cf->grid.nx,
+                        cf->grid.ny, psf, s);
+        prof.end();
+    }
+    if (e != hipSuccess) return dev_fail(e, psf ? "psf" : "grid");
+    return LR_OK;
+}
+
+lr_status lr_grid(const lr_cf *cf, const lr_vis *vis, lr_precision precision, void *grid,
+                  double *sumwt, int64_t *counters, void *work, size_t work_bytes,
+                  lr_stream stream) {
+    return grid_common(cf, vis, precision, grid, sumwt, counters, work, work_bytes, stream, 0);
+}
+
+lr_status lr_make_psf(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
+                      void *psf_grid, double *sumwt, int64_t *counters, void *work,
+                      size_t work_bytes, lr_stream stream) {
+    return grid_common(cf, vis, precision, psf_grid, sumwt, counters, work, work_bytes, stream,
+                       1);
+}
+
+lr_status lr_degrid(const lr_cf *cf, lr_vis *vis, lr_precision precision, const void *grid,
+                    int64_t *counters, void *work, size_t work_bytes, lr_stream stream) {
+    lr_status st = check_vis(cf, vis, true, false);
+    if (st != LR_OK) return st;
+    if ((st = check_precision(cf, precision)) != LR_OK) return st;
+    if (!grid) return fail(LR_E_ARG, "grid is NULL");
+    hipStream_t s = (hipStream_t)stream;
+    int64_t ng_bound = vis->plan ? vis->plan->n_groups : (int64_t)vis->nrow * vis->nchan;
+    size_t v_bytes = al256((size_t)std::max<int64_t>(ng_bound, 1) * vis->npol * cplx_bytes(precision));
+    size_t plan_need = vis->plan ? 0 : al256(plan_total(cf, vis));
+    if (work_bytes < plan_need + v_bytes)
+        return fail(LR_E_WORKSPACE, "workspace needs %zu bytes, got %zu", plan_need + v_bytes, work_bytes);
+    lr_plan tmp;
+    const lr_plan *P = nullptr;
+    size_t used = 0;
+    if ((st = resolve_plan(cf, vis, 0, work, work_bytes, s, tmp, P, used)) != LR_OK) return st;
+    void *Vg = (char *)work + used;
+    ProfileScope prof(s);
+    prof.begin();
+    hipError_t e = launch_degrid(P, view_of(cf), grid, Vg, precision, vis->npol, cf->grid.nx,
+                                 cf->grid.ny, s);
+    prof.end();
+    if (e == hipSuccess) e = launch_expand(P, Vg, vis->vis, vis->weight, precision, vis->npol, s);
+    if (e == hipSuccess && counters)
+        e = launch_counts(P, vis->weight, precision, vis->npol, nullptr, counters,
+                          cf->grid.nplane, s);
+    if (e != hipSuccess) return dev_fail(e, "degrid");
+    return LR_OK;
+}
+
+lr_status lr_sumwt(const lr_cf *cf, const lr_vis *vis, lr_precision precision, double *sumwt,
+                   int64_t *counters, void *work, size_t work_bytes, lr_stream stream) {
+    lr_status st = check_vis(cf, vis, false, true);
+    if (st != LR_OK) return st;
+    if ((st = check_precision(cf, precision)) != LR_OK) return st;
+    hipStream_t s = (hipStream_t)stream;
+    lr_plan tmp;
+    const lr_plan *P = nullptr;
+    size_t used = 0;
+    if ((st = resolve_plan(cf, vis, 0, work, work_bytes, s, tmp, P, used)) != LR_OK) return st;
+    hipError_t e = launch_counts(P, vis->weight, precision, vis->npol, sumwt, counters,
+                                 cf->grid.nplane, s);
+    if (e != hipSuccess) return dev_fail(e, "sumwt");
+    return LR_OK;
+}
+
+lr_status lr_debug_map(const lr_cf *cf, const lr_vis *vis, int psf, int32_t *out,
+                       lr_stream stream) {
+    lr_status st = check_vis(cf, vis, false, false);
+    if (st != LR_OK) return st;
+    if (!out && vis->nrow > 0) return fail(LR_E_ARG, "out is NULL");
+    std::vector<ChanConst> cc = chan_consts(cf, vis);
+    MapGeom g = map_geom(cf, vis->nchan, psf ? 1 : 0);
+    hipError_t e = launch_debug_map(vis->nrow, vis->nchan, vis->uvw, cc, g, out,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "debug map");
+    return LR_OK;
+}
+
+}  // extern "C"

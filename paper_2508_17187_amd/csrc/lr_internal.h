@@ -1,0 +1,134 @@
+// Internal declarations of the gfx950 gridding library: handle structs,
+// device parameter blocks and the per-sample index map shared by the
+// kernels.  Nothing here is part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "lr.h"
+
+namespace lr {
+
+constexpr double kCLight = 299792458.0;
+constexpr int kMaxChanPerUpload = 48;
+
+// ---------------------------------------------------------------------------
+// Per-channel constants formed on the host in FP64 (no contraction).
+struct ChanConst {
+    double kx, ky, kw;      // scale to 1/O-cell units and to w-plane units
+    double fscale;          // pi * D * nu / c, argument scale of the loss term
+    int32_t plane, fg;      // output plane (< 0: skipped), A-term group
+    int32_t pad0, pad1;
+};
+
+// Geometry the index map needs, passed by value to kernels.
+struct MapGeom {
+    int32_t nx, ny, O, n_w;
+    int32_t psf, npol, nplane, nchan;
+    double ox, oy, limx, limy;
+    const int32_t *h;       // device [n_w]
+};
+
+struct Map {
+    int32_t pu, pv, ou, ov, k, conj, keep;
+};
+
+// The index map of one (row, channel).  Exactly one rounding per coordinate
+// (fma), then floor and integer arithmetic only: bit-exact with a correct
+// host implementation of the same definition.
+__device__ __forceinline__ Map map_sample(double u, double v, double w, const ChanConst &cc,
+                                          const MapGeom &g) {
+    Map m;
+    m.pu = m.pv = m.ou = m.ov = m.k = m.conj = m.keep = 0;
+    double X = fma(u, cc.kx, g.ox);
+    double Y = fma(v, cc.ky, g.oy);
+    if (!(X >= 0.0 && X < g.limx) || !(Y >= 0.0 && Y < g.limy)) return m;
+    int32_t qx = (int32_t)floor(X);
+    int32_t qy = (int32_t)floor(Y);
+    int32_t half = g.O >> 1;
+    // q + O/2 >= 0 here, so C division is floor division
+    int32_t px = (qx + half) / g.O;
+    int32_t py = (qy + half) / g.O;
+    m.pu = px;
+    m.pv = py;
+    m.ou = qx - px * g.O;
+    m.ov = qy - py * g.O;
+    double kk = floor(fma(fabs(w), cc.kw, 0.5));
+    if (!(kk <= (double)(g.n_w - 1))) return m;
+    m.k = (int32_t)kk;
+    m.conj = (g.n_w > 1 && w < 0.0) ? 1 : 0;
+    int32_t h = g.h[m.k];
+    int32_t lo = g.psf ? 1 : 0;
+    if (px - h < lo || px + h > g.nx - 1) return m;
+    if (py - h < lo || py + h > g.ny - 1) return m;
+    m.keep = 1;
+    return m;
+}
+
+// ---------------------------------------------------------------------------
+// One group: kept (row, channel) pairs with identical plane, kernel and
+// footprint (and, with a pointing phasor, identical baseline and channel).
+struct GroupMeta {
+    int64_t cf_off;         // element offset of the S x S sub-kernel in the table
+    int64_t cell;           // P*npol*ny*nx + p_v*nx + p_u (pol 0)
+    int32_t pu, pv;
+    int32_t k, conj;        // w-plane, conjugate flag
+    int32_t ou, ov;         // oversampling offsets in [-O/2, O/2)
+    int32_t plane, fg;
+    double f;               // pointing loss factor (1 without phasor)
+    double bu, bv;          // phasor slopes du*dl/O and dv*dm/O (0 without)
+};
+
+// Device view of a CF table.
+struct CFView {
+    const void *table;
+    const int64_t *plane_off;   // [n_fg*n_w] element offsets
+    const float *scale;         // [n_fg*n_w] 2^-e (1 for f32 / f64)
+    const int32_t *h;           // [n_w]
+    int32_t O, n_w, n_fg, storage;
+};
+
+}  // namespace lr
+
+// ---------------------------------------------------------------------------
+// Host handles (opaque to callers).
+struct lr_cf {
+    lr_cf_spec spec;
+    std::vector<double> fg_hz;
+    lr_grid_spec grid;
+    int32_t M;
+    std::vector<int32_t> h;
+    std::vector<int64_t> plane_off;     // element offsets
+    int64_t n_elems;
+    size_t elem_bytes;
+    size_t header_bytes, total_bytes;
+    char *blob;                         // device
+    int32_t *d_h;
+    int64_t *d_plane_off;
+    int32_t *d_exp;
+    float *d_scale;
+    void *d_table;
+};
+
+struct lr_plan {
+    // what it was built for
+    const lr_cf *cf;
+    int64_t nrow;
+    int32_t nchan, npol, psf, po, merged;
+    std::vector<double> freq;
+    std::vector<int32_t> chan_plane, chan_fg;
+    // counts
+    int64_t n_pairs, n_kept, n_groups, n_ranges, n_tasks, taps;
+    // device arrays inside the caller's buffer
+    int32_t *order;            // [n_pairs] pair ids; kept (sorted) first; bit 30 set = skipped channel
+    int32_t *gidx;             // [n_kept] group of each sorted kept pair
+    int32_t *group_start;      // [n_groups + 1]
+    lr::GroupMeta *groups;     // [n_groups]
+    int32_t *r_g0;             // [n_ranges + 1] first group of each gridder range
+    int32_t *r_toff;           // [n_ranges + 1] first wavefront task of each range
+    size_t bytes_used;
+};

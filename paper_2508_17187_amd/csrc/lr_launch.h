@@ -1,0 +1,68 @@
+// Host-side launchers of the gfx950 kernels, called by the C ABI layer.
+#pragma once
+
+#include <vector>
+
+#include "lr_internal.h"
+
+namespace lr {
+
+// ---- plan (k_plan.hip) -------------------------------------------------------
+struct KeyLayout {
+    int32_t b_plane, b_fg, b_k, b_conj, b_pv, b_pu, b_bl, b_ch, b_o;
+    int32_t shift;     // right shift applied to the full key
+    int32_t end_bit;   // significant bits of the final key
+};
+
+struct PlanLayout {
+    size_t chan, order, gidx, group_start, groups, r_g0, r_toff, persistent;
+    size_t keys_a, keys_b, vals_a, flags, r_nch, counter, temp;
+    int64_t max_ranges;
+    size_t total;
+};
+
+hipError_t upload_chan(const std::vector<ChanConst> &cc, ChanConst *d, hipStream_t s);
+hipError_t upload_words(const void *src, size_t bytes, void *d, hipStream_t s);
+hipError_t launch_debug_map(int64_t nrow, int32_t nchan, const double *uvw,
+                            const std::vector<ChanConst> &cc, const MapGeom &g, int32_t *out,
+                            hipStream_t s);
+size_t sort_temp_bytes(int64_t n);
+PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t per, int64_t n_segments);
+hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const double *uvw,
+                             const ChanConst *d_cc, const MapGeom &g, const KeyLayout &kl,
+                             const CFView &cf, const int32_t *ant1, const int32_t *ant2,
+                             int32_t nant, const double *ant_dlm, double du_dl,
+                             double dv_dm, int32_t per, hipStream_t s);
+
+// ---- CF build (k_cf.hip) -----------------------------------------------------
+struct CFBuildArgs {
+    int32_t M, O, nx, ny, terms;
+    double cell_l, cell_m, c_ps, dish_m;
+};
+size_t cf_work_bytes(int32_t M, int32_t O, int32_t h_max);
+hipError_t launch_cf_build(const lr_cf *cf, const CFBuildArgs &a, void *work, hipStream_t s);
+
+// ---- hot path (k_grid.hip) ---------------------------------------------------
+hipError_t launch_zero(void *p, size_t bytes, hipStream_t s);
+
+struct VisArgs {
+    const void *vis;
+    const void *weight;
+    int32_t npol;
+    int32_t unit_vis;      // PSF: visibilities taken as 1
+};
+
+// presum: per group A[g][pol] = sum W V over its pairs; counters and sumwt
+hipError_t launch_presum(const lr_plan *P, const VisArgs &v, int precision, void *A,
+                         double *sumwt, int64_t *counters, int32_t nplane, hipStream_t s);
+hipError_t launch_counts(const lr_plan *P, const void *weight, int precision, int32_t npol,
+                         double *sumwt, int64_t *counters, int32_t nplane, hipStream_t s);
+hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
+                       int precision, int32_t npol, int32_t nx, int32_t ny, int32_t psf,
+                       hipStream_t s);
+hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
+                         int precision, int32_t npol, int32_t nx, int32_t ny, hipStream_t s);
+hipError_t launch_expand(const lr_plan *P, const void *Vg, void *vis, const void *weight,
+                         int precision, int32_t npol, hipStream_t s);
+
+}  // namespace lr

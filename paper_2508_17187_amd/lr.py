@@ -1,0 +1,352 @@
+"""ctypes binding of liblr.so (argument marshalling only).
+
+The functions keep the C names (lr_cf_build, lr_grid, lr_degrid,
+lr_make_psf, lr_sumwt, lr_debug_map, lr_plan_build, ...).  Device memory
+and streams come from PyTorch; every step of the computation runs in the
+library's HIP kernels.  There is no CPU fallback: importing this module
+without the built library raises.
+"""
+
+import ctypes as C
+import os
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblr.so")
+
+LR_OK, LR_E_ARG, LR_E_DTYPE, LR_E_WORKSPACE, LR_E_CF, LR_E_DEVICE, LR_E_RANGE = 0, -1, -2, -3, -4, -5, -6
+LR_F64, LR_F32, LR_F32_CF16, LR_F32_CFBF16 = 0, 1, 2, 3
+LR_TERM_PS, LR_TERM_W, LR_TERM_A = 1, 2, 4
+LR_OP_CF_BUILD, LR_OP_GRID, LR_OP_DEGRID, LR_OP_PSF, LR_OP_SUMWT = 0, 1, 2, 3, 4
+
+PRECISIONS = {"f64": LR_F64, "f32": LR_F32, "f16cf": LR_F32_CF16, "bf16cf": LR_F32_CFBF16}
+
+
+class LRError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (_status_name(status), msg))
+        self.status = status
+
+
+def _status_name(s):
+    return {0: "LR_OK", -1: "LR_E_ARG", -2: "LR_E_DTYPE", -3: "LR_E_WORKSPACE", -4: "LR_E_CF",
+            -5: "LR_E_DEVICE", -6: "LR_E_RANGE"}.get(s, "LR_E_%d" % s)
+
+
+class GridSpec(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("npol", C.c_int32),
+                ("nplane", C.c_int32), ("cell_l", C.c_double), ("cell_m", C.c_double)]
+
+
+class CFSpec(C.Structure):
+    _fields_ = [("terms", C.c_uint32), ("oversample", C.c_int32), ("ps_support", C.c_int32),
+                ("n_w", C.c_int32), ("w_max", C.c_double), ("h_min", C.c_int32),
+                ("h_max", C.c_int32), ("n_fg", C.c_int32), ("fg_hz", C.c_void_p),
+                ("dish_m", C.c_double), ("screen_m", C.c_int32), ("storage", C.c_int32)]
+
+
+class VisDesc(C.Structure):
+    _fields_ = [("nrow", C.c_int64), ("nchan", C.c_int32), ("npol", C.c_int32),
+                ("nant", C.c_int32), ("uvw", C.c_void_p), ("freq_hz", C.c_void_p),
+                ("chan_plane", C.c_void_p), ("chan_fg", C.c_void_p), ("vis", C.c_void_p),
+                ("weight", C.c_void_p), ("ant1", C.c_void_p), ("ant2", C.c_void_p),
+                ("ant_dlm", C.c_void_p), ("plan", C.c_void_p)]
+
+
+EXPORTS = {
+    "lr_cf_bytes": (C.c_size_t, [C.c_void_p, C.c_void_p]),
+    "lr_workspace_bytes": (C.c_size_t, [C.c_int, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int]),
+    "lr_cf_build": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p,
+                              C.c_size_t, C.c_void_p, C.c_void_p]),
+    "lr_cf_attach": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "lr_cf_free": (None, [C.c_void_p]),
+    "lr_cf_scale_exponents": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lr_cf_layout": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lr_plan_bytes": (C.c_size_t, [C.c_void_p, C.c_void_p, C.c_int]),
+    "lr_plan_build": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
+                                C.c_void_p, C.c_void_p]),
+    "lr_plan_free": (None, [C.c_void_p]),
+    "lr_plan_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lr_set_profile_events": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lr_grid": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                          C.c_void_p, C.c_size_t, C.c_void_p]),
+    "lr_degrid": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                            C.c_void_p, C.c_size_t, C.c_void_p]),
+    "lr_make_psf": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "lr_sumwt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.c_size_t, C.c_void_p]),
+    "lr_debug_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "lr_status_str": (C.c_char_p, [C.c_int]),
+    "lr_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load liblr.so; raises when it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("liblr.so is not built (run python -m paper_2508_17187_amd.build); "
+                              "there is no fallback path")
+        l = C.CDLL(LIB_PATH)
+        for name, (res, args) in EXPORTS.items():
+            f = getattr(l, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = l
+    return _lib
+
+
+def _check(status):
+    if status != LR_OK:
+        raise LRError(status, lib().lr_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _vis_dtype(precision):
+    return (torch.complex128, torch.float64) if precision == LR_F64 else (torch.complex64,
+                                                                          torch.float32)
+
+
+# ---------------------------------------------------------------------------
+class CF:
+    """A CF table built on the GPU (lr_cf_build) and its host handle."""
+
+    def __init__(self, grid, spec, device="cuda", stream=None, blob=None):
+        self.grid = grid if isinstance(grid, GridSpec) else GridSpec(*grid)
+        self.fg = np.ascontiguousarray(spec.pop("fg_hz"), np.float64)
+        self.spec = CFSpec(fg_hz=self.fg.ctypes.data, **spec)
+        self.precision = self.spec.storage
+        L = lib()
+        nbytes = L.lr_cf_bytes(C.byref(self.spec), C.byref(self.grid))
+        if nbytes == 0:
+            raise LRError(LR_E_ARG, L.lr_last_error().decode())
+        self.nbytes = nbytes
+        self.handle = C.c_void_p()
+        if blob is None:
+            self.blob = torch.empty(nbytes, dtype=torch.uint8, device=device)
+            wb = L.lr_workspace_bytes(LR_OP_CF_BUILD, C.byref(self.spec), C.byref(self.grid),
+                                      None, self.precision)
+            work = torch.empty(max(wb, 1), dtype=torch.uint8, device=device)
+            _check(L.lr_cf_build(C.byref(self.spec), C.byref(self.grid), _ptr(self.blob),
+                                 nbytes, _ptr(work), wb, _stream(stream),
+                                 C.byref(self.handle)))
+            self._work = work      # kept until the build has run on the stream
+        else:
+            self.blob = blob
+            _check(L.lr_cf_attach(C.byref(self.spec), C.byref(self.grid), _ptr(blob),
+                                  blob.numel(), C.byref(self.handle)))
+
+    def layout(self):
+        off, eb, ne = C.c_size_t(), C.c_size_t(), C.c_int64()
+        po = np.zeros(self.spec.n_fg * self.spec.n_w, np.int64)
+        _check(lib().lr_cf_layout(self.handle, C.byref(off), C.byref(eb), C.byref(ne),
+                                  po.ctypes.data_as(C.c_void_p)))
+        return off.value, eb.value, ne.value, po
+
+    def table_host(self):
+        """The stored table decoded to complex128 on the host (test hook):
+        fp16 / bf16 entries are divided by their plane's 2^e."""
+        off, eb, ne, po = self.layout()
+        raw = self.blob[off:off + eb * ne].cpu().numpy()
+        if eb == 16:
+            return raw.view(np.complex128).copy()
+        if eb == 8:
+            return raw.view(np.complex64).astype(np.complex128)
+        u = raw.view(np.uint32)
+        if self.precision == LR_F32_CF16:
+            re = (u & 0xFFFF).astype(np.uint16).view(np.float16).astype(np.float64)
+            im = (u >> 16).astype(np.uint16).view(np.float16).astype(np.float64)
+        else:
+            re = ((u & 0xFFFF) << 16).astype(np.uint32).view(np.float32).astype(np.float64)
+            im = (u & 0xFFFF0000).astype(np.uint32).view(np.float32).astype(np.float64)
+        out = re + 1j * im
+        ex = self.scale_exponents()
+        bounds = list(po) + [ne]
+        for i in range(len(po)):
+            out[bounds[i]:bounds[i + 1]] = np.ldexp(out[bounds[i]:bounds[i + 1]].real, -int(ex[i])) \
+                + 1j * np.ldexp(out[bounds[i]:bounds[i + 1]].imag, -int(ex[i]))
+        return out
+
+    def scale_exponents(self, stream=None):
+        n = self.spec.n_fg * self.spec.n_w
+        out = np.zeros(n, np.int32)
+        _check(lib().lr_cf_scale_exponents(self.handle, out.ctypes.data_as(C.c_void_p),
+                                           _stream(stream)))
+        return out
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().lr_cf_free(self.handle)
+                self.handle = C.c_void_p()
+        except Exception:
+            pass
+
+
+class Vis:
+    """Visibility data on the device plus the host channel tables.
+
+    uvw: [nrow, 3] float64 tensor; freq_hz, chan_plane, chan_fg: host arrays;
+    vis / weight: [nrow, nchan, npol] tensors (complex128/float64 or
+    complex64/float32); ant1, ant2 (int32 [nrow]) and ant_dlm (float64
+    [nant, 2]) switch the pointing phasor on."""
+
+    def __init__(self, uvw, freq_hz, chan_plane=None, chan_fg=None, vis=None, weight=None,
+                 npol=None, ant1=None, ant2=None, ant_dlm=None, plan=None):
+        self.uvw = uvw
+        self.freq = np.ascontiguousarray(freq_hz, np.float64)
+        nchan = self.freq.shape[0]
+        self.chan_plane = np.ascontiguousarray(
+            np.zeros(nchan) if chan_plane is None else chan_plane, np.int32)
+        self.chan_fg = None if chan_fg is None else np.ascontiguousarray(chan_fg, np.int32)
+        self.vis = vis
+        self.weight = weight
+        self.npol = npol if npol is not None else (vis.shape[-1] if vis is not None else
+                                                   weight.shape[-1])
+        self.ant1, self.ant2, self.ant_dlm = ant1, ant2, ant_dlm
+        self.plan = plan
+
+    @property
+    def nrow(self):
+        return int(self.uvw.shape[0])
+
+    @property
+    def nchan(self):
+        return int(self.freq.shape[0])
+
+    def desc(self):
+        d = VisDesc()
+        d.nrow = self.nrow
+        d.nchan = self.nchan
+        d.npol = self.npol
+        d.nant = 0 if self.ant_dlm is None else int(self.ant_dlm.shape[0])
+        d.uvw = self.uvw.data_ptr()
+        d.freq_hz = self.freq.ctypes.data
+        d.chan_plane = self.chan_plane.ctypes.data
+        d.chan_fg = None if self.chan_fg is None else self.chan_fg.ctypes.data
+        d.vis = None if self.vis is None else self.vis.data_ptr()
+        d.weight = None if self.weight is None else self.weight.data_ptr()
+        d.ant1 = None if self.ant1 is None else self.ant1.data_ptr()
+        d.ant2 = None if self.ant2 is None else self.ant2.data_ptr()
+        d.ant_dlm = None if self.ant_dlm is None else self.ant_dlm.data_ptr()
+        d.plan = None if self.plan is None else self.plan.handle.value
+        return d
+
+    def with_(self, **kw):
+        import copy
+        v = copy.copy(self)
+        for k, x in kw.items():
+            setattr(v, k, x)
+        return v
+
+
+class Plan:
+    """Binning plan (lr_plan_build) in a device buffer owned by this object."""
+
+    def __init__(self, cf, vis, psf=False, stream=None):
+        L = lib()
+        v = vis.with_(plan=None)
+        d = v.desc()
+        n = L.lr_plan_bytes(cf.handle, C.byref(d), int(psf))
+        if n == 0:
+            raise LRError(LR_E_ARG, L.lr_last_error().decode())
+        self.buf = torch.empty(n, dtype=torch.uint8, device=vis.uvw.device)
+        self.handle = C.c_void_p()
+        self.cf = cf
+        self.psf = bool(psf)
+        _check(L.lr_plan_build(cf.handle, C.byref(d), int(psf), _ptr(self.buf), n,
+                               _stream(stream), C.byref(self.handle)))
+
+    def info(self):
+        a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
+        _check(lib().lr_plan_info(self.handle, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return {"n_groups": a.value, "n_kept": b.value, "n_pairs": c.value, "taps": d.value}
+
+    def __del__(self):
+        try:
+            if self.handle:
+                lib().lr_plan_free(self.handle)
+                self.handle = C.c_void_p()
+        except Exception:
+            pass
+
+
+def workspace_bytes(op, cf, vis, precision):
+    d = vis.desc()
+    return lib().lr_workspace_bytes(op, C.byref(cf.spec), C.byref(cf.grid), C.byref(d), precision)
+
+
+def _work(op, cf, vis, precision, work):
+    n = workspace_bytes(op, cf, vis, precision)
+    if n == 0:
+        raise LRError(LR_E_ARG, lib().lr_last_error().decode())
+    if work is None or work.numel() < n:
+        work = torch.empty(n, dtype=torch.uint8, device=vis.uvw.device)
+    return work
+
+
+def lr_grid(cf, vis, precision, grid, sumwt=None, counters=None, work=None, stream=None):
+    work = _work(LR_OP_GRID, cf, vis, precision, work)
+    d = vis.desc()
+    _check(lib().lr_grid(cf.handle, C.byref(d), precision, _ptr(grid), _ptr(sumwt),
+                         _ptr(counters), _ptr(work), work.numel(), _stream(stream)))
+    return work
+
+
+def lr_degrid(cf, vis, precision, grid, counters=None, work=None, stream=None):
+    work = _work(LR_OP_DEGRID, cf, vis, precision, work)
+    d = vis.desc()
+    _check(lib().lr_degrid(cf.handle, C.byref(d), precision, _ptr(grid), _ptr(counters),
+                           _ptr(work), work.numel(), _stream(stream)))
+    return work
+
+
+def lr_make_psf(cf, vis, precision, psf_grid, sumwt=None, counters=None, work=None,
+                stream=None):
+    work = _work(LR_OP_PSF, cf, vis, precision, work)
+    d = vis.desc()
+    _check(lib().lr_make_psf(cf.handle, C.byref(d), precision, _ptr(psf_grid), _ptr(sumwt),
+                             _ptr(counters), _ptr(work), work.numel(), _stream(stream)))
+    return work
+
+
+def lr_sumwt(cf, vis, precision, sumwt, counters=None, work=None, stream=None):
+    work = _work(LR_OP_SUMWT, cf, vis, precision, work)
+    d = vis.desc()
+    _check(lib().lr_sumwt(cf.handle, C.byref(d), precision, _ptr(sumwt), _ptr(counters),
+                          _ptr(work), work.numel(), _stream(stream)))
+    return work
+
+
+def lr_debug_map(cf, vis, psf=False, stream=None):
+    out = torch.empty((vis.nrow, vis.nchan, 8), dtype=torch.int32, device=vis.uvw.device)
+    d = vis.desc()
+    _check(lib().lr_debug_map(cf.handle, C.byref(d), int(psf), _ptr(out), _stream(stream)))
+    return out
+
+
+def lr_set_profile_events(start, stop):
+    """start / stop: hipEvent_t handles as ints (or None, None)."""
+    _check(lib().lr_set_profile_events(start, stop))
+
+
+def lr_cf_build(grid, spec, device="cuda", stream=None):
+    return CF(grid, dict(spec), device=device, stream=stream)
+
+
+def lr_plan_build(cf, vis, psf=False, stream=None):
+    return Plan(cf, vis, psf=psf, stream=stream)

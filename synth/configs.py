@@ -73,7 +73,7 @@ def max_abs_w_lambda(obs):
 def _build(name, *, n_ant, diameter_m, n_time, dt_s, dec_deg, freq_hz, npol,
            n_src, sigma, grid, cf, cfg_id, chan_plane=None, chan_fg=None,
            sky_half_width_deg=0.5, flux=(0.1, 1.0), log_flux=False,
-           with_vis=True, pointing_sigma=0.0):
+           with_vis=True, pointing_sigma=0.0, dft_device="cpu"):
     obs = make_observation(n_ant, diameter_m, n_time, dt_s, dec_deg, freq_hz,
                            seed=1000 + cfg_id)
     sky = random_point_sky(n_src, seed=2000 + cfg_id,
@@ -81,7 +81,7 @@ def _build(name, *, n_ant, diameter_m, n_time, dt_s, dec_deg, freq_hz, npol,
                            flux_lo=flux[0], flux_hi=flux[1], log_flux=log_flux)
     nchan = obs.nchan
     if with_vis:
-        v = dft_visibilities(obs.uvw, obs.freq_hz, sky, npol)
+        v = dft_visibilities(obs.uvw, obs.freq_hz, sky, npol, device=dft_device)
         if sigma > 0:
             v, wt = add_noise(v, sigma, seed=3000 + cfg_id)
         else:
@@ -118,7 +118,7 @@ def config1_plain():
                   sigma=0.01, grid=grid, cf=cf, cfg_id=1)
 
 
-def config2_wproj(with_vis=True, n_time=600, nchan=16):
+def config2_wproj(with_vis=True, n_time=600, nchan=16, dft_device="cpu"):
     """W-projection: 351 baselines of a 36 km disc, 600 dumps over 10 s,
     16 channels over 2-4 GHz, 4 correlations (13,478,400 samples), 200
     sources, sigma 0.01 Jy.  32 w-planes, supports 17..65, O=20, on a
@@ -130,20 +130,20 @@ def config2_wproj(with_vis=True, n_time=600, nchan=16):
     return _build("config2_wproj", n_ant=27, diameter_m=36000.0, n_time=n_time,
                   dt_s=10.0 / 600, dec_deg=30.0, freq_hz=channel_freqs(nchan),
                   npol=4, n_src=200, sigma=0.01, grid=grid, cf=cf, cfg_id=2,
-                  with_vis=with_vis)
+                  with_vis=with_vis, dft_device=dft_device)
 
 
-def config2_ps(with_vis=True, n_time=600, nchan=16):
+def config2_ps(with_vis=True, n_time=600, nchan=16, dft_device="cpu"):
     """The W-projection data gridded with the Standard (PS only) kernel,
     S=7, O=100: the shape on which HBM bandwidth binds."""
-    w = config2_wproj(with_vis=with_vis, n_time=n_time, nchan=nchan)
+    w = config2_wproj(with_vis=with_vis, n_time=n_time, nchan=nchan, dft_device=dft_device)
     w.name = "config2_ps"
     w.cf = CFSetup(terms=TERM_PS, oversample=100, ps_support=7, n_w=1, w_max=0.0,
                    h_min=3, h_max=3, fg_hz=np.array([3.0e9]))
     return w
 
 
-def config3_awproj(with_vis=True, n_time=600, nchan=64, n_fg=8):
+def config3_awproj(with_vis=True, n_time=600, nchan=64, n_fg=8, dft_device="cpu"):
     """A+W projection: the W-projection layout over 64 channels and 4
     correlations with per-antenna Airy A-terms (25 m dishes) in 8 frequency
     groups and random pointing offsets of 1% of the 3 GHz FWHM per axis."""
@@ -158,7 +158,7 @@ def config3_awproj(with_vis=True, n_time=600, nchan=64, n_fg=8):
     return _build("config3_awproj", n_ant=27, diameter_m=36000.0, n_time=n_time,
                   dt_s=10.0 / 600, dec_deg=30.0, freq_hz=freq, npol=4, n_src=200,
                   sigma=0.01, grid=grid, cf=cf, cfg_id=3, chan_fg=chan_fg,
-                  with_vis=with_vis, pointing_sigma=0.01 * fwhm)
+                  with_vis=with_vis, pointing_sigma=0.01 * fwhm, dft_device=dft_device)
 
 
 def config5_chunk(n_time=1085, nchan=64, with_vis=False):

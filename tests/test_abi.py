@@ -1,0 +1,124 @@
+"""The C ABI on a machine without a GPU: every symbol include/lr.h declares
+is exported, and host-side validation rejects malformed calls with the
+documented status before anything touches a device."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2508_17187_amd import lr
+    if not os.path.exists(lr.LIB_PATH):
+        from paper_2508_17187_amd import build
+        build.build()
+    return lr
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "lr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"\b(lr_[a-z_0-9]+)\s*\(", src)
+    return sorted(set(names))
+
+
+def test_every_declared_symbol_is_exported(L):
+    names = declared_functions()
+    assert len(names) >= 15
+    lib = L.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(L.EXPORTS), set(names) ^ set(L.EXPORTS)
+
+
+def _specs(L, **over):
+    g = L.GridSpec(256, 256, 4, 1, 1e-6, 1e-6)
+    fg = np.array([3e9])
+    s = dict(terms=3, oversample=20, ps_support=7, n_w=8, w_max=1e4, h_min=3, h_max=8,
+             n_fg=1, fg_hz=fg.ctypes.data, dish_m=25.0, screen_m=0, storage=L.LR_F32)
+    s.update(over)
+    return g, L.CFSpec(**s), fg
+
+
+def test_sizes_are_host_only_and_match_the_layout(L):
+    g, s, fg = _specs(L)
+    lib = L.lib()
+    n = lib.lr_cf_bytes(C.byref(s), C.byref(g))
+    h = [3 + (2 * 5 * k + 7) // 14 for k in range(8)]
+    elems = sum(21 * 21 * (2 * x + 1) ** 2 for x in h)
+    assert n >= elems * 8 and n < elems * 8 + 4096
+    s.storage = L.LR_F32_CF16
+    assert lib.lr_cf_bytes(C.byref(s), C.byref(g)) < n
+    assert lib.lr_workspace_bytes(L.LR_OP_CF_BUILD, C.byref(s), C.byref(g), None, 2) > 0
+
+
+@pytest.mark.parametrize("field,value,msg", [
+    ("oversample", 3, "oversample"), ("n_w", 0, "n_w"), ("terms", 0, "terms"),
+    ("h_max", 200, "h_min"), ("w_max", -1.0, "w_max"), ("storage", 9, "storage"),
+    ("screen_m", 7, "screen_m"),
+])
+def test_invalid_cf_specs_are_rejected(L, field, value, msg):
+    g, s, fg = _specs(L, **{field: value})
+    lib = L.lib()
+    assert lib.lr_cf_bytes(C.byref(s), C.byref(g)) == 0
+    assert msg in lib.lr_last_error().decode()
+    h = C.c_void_p()
+    st = lib.lr_cf_build(C.byref(s), C.byref(g), C.c_void_p(16), 1 << 30, C.c_void_p(16),
+                         1 << 30, None, C.byref(h))
+    assert st in (L.LR_E_ARG, L.LR_E_DTYPE)
+    assert not h.value
+
+
+def test_invalid_grid_specs_are_rejected(L):
+    lib = L.lib()
+    for nx, npol in ((7, 4), (256, 3), (20000, 4)):
+        g, s, fg = _specs(L)
+        g.nx, g.npol = nx, npol
+        assert lib.lr_cf_bytes(C.byref(s), C.byref(g)) == 0
+
+
+def test_call_validation_before_any_device_work(L):
+    lib = L.lib()
+    g, s, fg = _specs(L)
+    n = lib.lr_cf_bytes(C.byref(s), C.byref(g))
+    h = C.c_void_p()
+    # attach touches no device memory: a fake pointer is fine for validation
+    assert lib.lr_cf_attach(C.byref(s), C.byref(g), C.c_void_p(4096), n, C.byref(h)) == L.LR_OK
+    assert lib.lr_cf_attach(C.byref(s), C.byref(g), C.c_void_p(4096), n - 1,
+                            C.byref(C.c_void_p())) == L.LR_E_CF
+    freq = np.array([3e9, 3.1e9])
+    cp = np.array([0, 0], np.int32)
+    d = L.VisDesc(nrow=10, nchan=2, npol=2, nant=0, uvw=4096, freq_hz=freq.ctypes.data,
+                  chan_plane=cp.ctypes.data, chan_fg=None, vis=4096, weight=4096)
+    st = lib.lr_grid(h, C.byref(d), L.LR_F32, C.c_void_p(4096), None, None, None, 0, None)
+    assert st == L.LR_E_ARG and b"npol" in lib.lr_last_error()
+    d.npol = 4
+    st = lib.lr_grid(h, C.byref(d), L.LR_F64, C.c_void_p(4096), None, None, None, 0, None)
+    assert st == L.LR_E_DTYPE
+    cp[1] = 5
+    st = lib.lr_degrid(h, C.byref(d), L.LR_F32, C.c_void_p(4096), None, None, 0, None)
+    assert st == L.LR_E_ARG and b"chan_plane" in lib.lr_last_error()
+    cp[1] = 0
+    st = lib.lr_grid(h, C.byref(d), L.LR_F32, None, None, None, None, 0, None)
+    assert st == L.LR_E_ARG
+    st = lib.lr_grid(h, C.byref(d), L.LR_F32, C.c_void_p(4096), None, None, C.c_void_p(4096),
+                     16, None)
+    assert st == L.LR_E_WORKSPACE
+    d.ant1 = 4096
+    st = lib.lr_grid(h, C.byref(d), L.LR_F32, C.c_void_p(4096), None, None, None, 0, None)
+    assert st == L.LR_E_ARG and b"pointing" in lib.lr_last_error()
+    lib.lr_cf_free(h)
+    assert lib.lr_status_str(L.LR_E_WORKSPACE) == b"LR_E_WORKSPACE"
+
+
+def test_binding_fails_loudly_without_the_library(L, monkeypatch, tmp_path):
+    monkeypatch.setattr(L, "_lib", None)
+    monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
+    with pytest.raises(ImportError):
+        L.lib()

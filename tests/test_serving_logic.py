@@ -1,0 +1,165 @@
+"""Serving logic on the CPU: the admission scheduler under a simulated clock
+and the threaded request loop with a fake executor (no GPU)."""
+
+import heapq
+import threading
+import time
+
+import numpy as np
+import pytest
+
+from paper_2508_17187_amd.serving import (Job, Scheduler, Server, cf_bytes, job_bytes,
+                                          latency_stats)
+
+
+def simulate(jobs, budget, n_slots, duration, fail_ids=()):
+    """Event-driven run: arrivals at job.t_arrival, completion after
+    duration(job).  Returns the scheduler and a trace of (time, used)."""
+    s = Scheduler(budget, n_slots)
+    ev = [(j.t_arrival, 0, j.job_id, j) for j in jobs]
+    heapq.heapify(ev)
+    trace = []
+    order = []
+    while ev:
+        t, kind, _, j = heapq.heappop(ev)
+        if kind == 0:
+            s.submit(j, t)
+        else:
+            s.complete(j, t, "injected" if j.job_id in fail_ids else None)
+        for job, new_cf in s.admit(t):
+            order.append(job.job_id)
+            heapq.heappush(ev, (t + duration(job), 1, job.job_id, job))
+        trace.append((t, s.used, len(s.running)))
+        assert s.used <= s.budget
+        assert len(s.running) <= n_slots
+    return s, trace, order
+
+
+def stream(n, rate=20.0, seed=0):
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1 / rate, n))
+    jobs = []
+    for i in range(n):
+        nvis = int(10 ** rng.uniform(4, 7.3))
+        ng = int(rng.choice([512, 1024, 2048, 4096]))
+        nw = int(rng.integers(1, 65))
+        key = (ng, nw)
+        jobs.append(Job(i, "grid" if rng.random() < 0.5 else "degrid", key,
+                        job_bytes(nvis // 4, 1, 4, ng), cf_bytes(nw, 8, 32, 20) if nw > 1 else
+                        cf_bytes(1, 3, 3, 100), n_vis=nvis, t_arrival=float(t[i])))
+    return jobs
+
+
+def test_budget_slots_and_arrival_order_hold():
+    jobs = stream(256)
+    budget = 16 << 30
+    s, trace, order = simulate(jobs, budget, 4, lambda j: 2e-8 * j.n_vis + 0.05)
+    assert len(s.done) == 256 and not s.rejected
+    assert order == sorted(order)                 # admitted in arrival order
+    assert max(u for _, u, _ in trace) <= budget
+    assert max(r for _, _, r in trace) == 4      # the slots are all used
+    st = latency_stats(s.done)
+    assert st["p99_s"] >= st["p50_s"] > 0
+
+
+def test_jobs_arriving_during_others_are_admitted_as_resources_free():
+    # slot-bound: three long jobs, then a short one arrives while they run
+    jobs = [Job(i, "grid", ("k", i), 100, 10, n_vis=1, t_arrival=0.0) for i in range(3)]
+    jobs.append(Job(3, "grid", ("k", 3), 100, 10, n_vis=1, t_arrival=0.5))
+    dur = {0: 3.0, 1: 1.0, 2: 2.0, 3: 0.1}
+    s, _, _ = simulate(jobs, 1000, 3, lambda j: dur[j.job_id])
+    j3 = [j for j in s.done if j.job_id == 3][0]
+    assert j3.t_admit == pytest.approx(1.0)      # the first slot to free up
+    # memory-bound: the late job waits for bytes, not slots
+    jobs = [Job(0, "grid", "a", 600, 0, t_arrival=0.0),
+            Job(1, "grid", "a", 600, 0, t_arrival=0.1)]
+    s, _, _ = simulate(jobs, 1000, 4, lambda j: 2.0)
+    j1 = [j for j in s.done if j.job_id == 1][0]
+    assert j1.t_admit == pytest.approx(2.0)
+
+
+def test_resident_cf_is_shared_and_evicted_lru_when_budget_binds():
+    s = Scheduler(1000, 4)
+    a = Job(0, "grid", "A", 100, 300, t_arrival=0)
+    b = Job(1, "grid", "A", 100, 300, t_arrival=0)
+    s.submit(a, 0), s.submit(b, 0)
+    adm = s.admit(0)
+    assert [n for _, n in adm] == [True, False]   # one CF for both
+    assert s.used == 500
+    s.complete(a, 1), s.complete(b, 1)
+    assert s.used == 300 and "A" in s.cf          # stays resident when idle
+    c = Job(2, "grid", "B", 100, 700, t_arrival=2)
+    s.submit(c, 2)
+    adm = s.admit(2)
+    assert adm and "A" not in s.cf and s.used == 800   # A evicted for B
+
+
+def test_oversized_job_is_rejected_alone_and_failures_are_isolated():
+    jobs = stream(40, seed=3)
+    big = Job(99, "grid", "huge", 10 << 40, 0, t_arrival=0.2)
+    s, _, _ = simulate(jobs + [big], 16 << 30, 4, lambda j: 0.01, fail_ids={5, 6})
+    assert [j.job_id for j in s.rejected] == [99]
+    failed = sorted(j.job_id for j in s.done if j.error)
+    assert failed == [5, 6]
+    assert len([j for j in s.done if not j.error]) == 38
+    assert s.used == sum(e[0] for e in s.cf.values())   # only resident CFs remain
+
+
+class FakeExecutor:
+    """Sleeps for a duration proportional to the job; optional failures."""
+
+    def __init__(self, fail=()):
+        self.fail = set(fail)
+        self.cfs = set()
+        self.concurrency = 0
+        self.max_concurrency = 0
+        self.lock = threading.Lock()
+
+    def has_cf(self, key):
+        return key in self.cfs
+
+    def prepare_cf(self, job, slot):
+        time.sleep(0.005)
+        if job.job_id in self.fail and job.op == "cf":
+            raise RuntimeError("cf build failed")
+        self.cfs.add(job.cf_key)
+
+    def release_cf(self, key):
+        self.cfs.discard(key)
+
+    def run(self, job, slot):
+        with self.lock:
+            self.concurrency += 1
+            self.max_concurrency = max(self.max_concurrency, self.concurrency)
+        try:
+            time.sleep(0.002 + 1e-9 * job.n_vis)
+            if job.job_id in self.fail:
+                raise RuntimeError("injected fault")
+            return job.job_id * 2
+        finally:
+            with self.lock:
+                self.concurrency -= 1
+
+
+def test_threaded_server_with_fake_executor():
+    exe = FakeExecutor(fail={7})
+    srv = Server(exe, hbm_budget=16 << 30, n_slots=4)
+    jobs = stream(48, rate=400.0, seed=4)
+    futs = []
+    for j in jobs:
+        futs.append(srv.submit(j))
+        time.sleep(0.001)
+    srv.drain(timeout=60)
+    ok = 0
+    for j, f in zip(jobs, futs):
+        if j.job_id == 7:
+            with pytest.raises(RuntimeError):
+                f.result(timeout=1)
+        else:
+            assert f.result(timeout=1).result == j.job_id * 2
+            ok += 1
+    st = srv.stats()
+    srv.close()
+    assert ok == 47 and st["jobs_done"] == 47 and st["jobs_failed"] == 1
+    assert exe.max_concurrency > 1                  # work overlapped
+    assert st["peak_hbm_bytes"] <= st["hbm_budget"]
