@@ -5,19 +5,20 @@
 //   presum   for every group of samples that share plane, kernel and
 //            footprint, A_g = sum W V (exact regrouping of the sum; FP32 or
 //            FP64), together with the class counters and FP64 sum of weights;
-//   grid     one wavefront task = 64 of the S*S residue classes of the
-//            support (cell x mod S, cell y mod S) over a run of groups of one
-//            w-plane sorted by pixel.  Each lane owns one grid cell at a time
-//            and accumulates Ct(o, t) phi(t) A_g for it in registers; only when
-//            the footprint moves off that cell does the lane flush its
-//            accumulator to HBM with atomics.  Group data are wave-uniform
-//            (scalar loads), the kernel tap is one vector load per lane.
+//   grid     one workgroup per chunk of the (tile, group) pairs of a 32 x 32
+//            cell tile.  Each thread owns four cells of the tile and
+//            accumulates Ct(o, t) phi(t) A_g over every group covering them in
+//            registers; the tile is written once at the end, with plain loads
+//            and stores when the chunk owns the whole tile.  Group data are
+//            workgroup-uniform (scalar loads); a kernel tap is one vector load.
 // Degridding D (Eq. ME-MOD-GRIDDED):
 //   degrid   one wavefront per group gathers sum_t conj(Ct phi) grid over the
 //            footprint (lanes over taps, coalesced along t_u) and reduces
 //            across lanes;
 //   expand   writes each group's value to every sample of the group (0 for
 //            flagged, skipped and dropped samples).
+#include <algorithm>
+
 #include "lr_internal.h"
 #include "lr_launch.h"
 
@@ -146,50 +147,48 @@ __device__ __forceinline__ long long wave_sum_ll(long long v) {
 }
 
 // ---------------------------------------------------------------------------
-// presum + counters: one thread per group; then the non-kept pairs.
+// presum + counters: one thread per sorted kept pair, a segmented scan over
+// the wavefront by group, one atomic per group segment of the wave (into A,
+// zeroed beforehand); threads past the kept pairs count the dropped and
+// skipped ones.
 template <typename T, int NPOL, bool UNIT, bool SUMS>
 __global__ __launch_bounds__(256) void k_presum(
-    int64_t n_groups, int64_t n_kept, int64_t n_pairs, const int32_t *order,
-    const int32_t *group_start, const GroupMeta *groups, const T *vis, const T *weight,
-    cpx<T> *A, double *sumwt, long long *counters) {
-    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t n_kept, int64_t n_pairs, const int32_t *order, const int32_t *gidx,
+    const GroupMeta *groups, const T *vis, const T *weight, cpx<T> *A, double *sumwt,
+    long long *counters) {
+    const int lane = threadIdx.x & 63;
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     long long kept = 0, flagged = 0, dropped = 0;
     double sw[NPOL];
-    int plane = -1;
-    for (int p = 0; p < NPOL; ++p) sw[p] = 0.0;
-    if (g < n_groups) {
-        int32_t i0 = group_start[g], i1 = group_start[g + 1];
+    cpx<T> a[NPOL];
+    for (int p = 0; p < NPOL; ++p) {
+        sw[p] = 0.0;
+        a[p] = {(T)0, (T)0};
+    }
+    int g = -1, plane = -1;
+    if (i < n_kept) {
+        g = gidx[i];
         plane = groups[g].plane;
-        cpx<T> acc[NPOL];
-        for (int p = 0; p < NPOL; ++p) acc[p] = {(T)0, (T)0};
-        for (int32_t i = i0; i < i1; ++i) {
-            int64_t pair = order[i];
-            for (int p = 0; p < NPOL; ++p) {
-                T W = weight ? weight[pair * NPOL + p] : (T)1;
-                if (W != (T)0) {
-                    ++kept;
-                    sw[p] += (double)W;
-                    if (SUMS) {
-                        if (UNIT) {
-                            acc[p].x += W;
-                        } else {
-                            const T *v = vis + 2 * (pair * NPOL + p);
-                            acc[p].x = fma(W, v[0], acc[p].x);
-                            acc[p].y = fma(W, v[1], acc[p].y);
-                        }
+        int64_t pair = order[i];
+        for (int p = 0; p < NPOL; ++p) {
+            T W = weight ? weight[pair * NPOL + p] : (T)1;
+            if (W != (T)0) {
+                ++kept;
+                sw[p] = (double)W;
+                if (SUMS) {
+                    if (UNIT) {
+                        a[p].x = W;
+                    } else {
+                        const T *v = vis + 2 * (pair * NPOL + p);
+                        a[p].x = W * v[0];
+                        a[p].y = W * v[1];
                     }
-                } else {
-                    ++flagged;
                 }
+            } else {
+                ++flagged;
             }
         }
-        if (SUMS)
-            for (int p = 0; p < NPOL; ++p) A[g * NPOL + p] = acc[p];
-    }
-    // pairs that were dropped or skipped at binning
-    int64_t nt = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = n_kept + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n_pairs;
-         i += nt) {
+    } else if (i < n_pairs) {
         int32_t v = order[i];
         bool skipped = (v >> 30) & 1;
         int64_t pair = v & ~(1 << 30);
@@ -198,26 +197,46 @@ __global__ __launch_bounds__(256) void k_presum(
             if (skipped || W == (T)0) ++flagged; else ++dropped;
         }
     }
+    if (SUMS) {
+        // segmented inclusive scan by group id across the wavefront
+        for (int off = 1; off < 64; off <<= 1) {
+            int go = __shfl_up(g, off);
+            bool take = lane >= off && go == g;
+            for (int p = 0; p < NPOL; ++p) {
+                T x = __shfl_up(a[p].x, off), y = __shfl_up(a[p].y, off);
+                if (take) {
+                    a[p].x += x;
+                    a[p].y += y;
+                }
+            }
+        }
+        int gn = __shfl_down(g, 1);
+        bool last = (lane == 63) || gn != g;
+        if (g >= 0 && last)
+            for (int p = 0; p < NPOL; ++p) {
+                atomicAdd(&A[(int64_t)g * NPOL + p].x, a[p].x);
+                if (!UNIT) atomicAdd(&A[(int64_t)g * NPOL + p].y, a[p].y);
+            }
+    }
     if (counters) {
         kept = wave_sum_ll(kept);
         flagged = wave_sum_ll(flagged);
         dropped = wave_sum_ll(dropped);
-        if ((threadIdx.x & 63) == 0) {
+        if (lane == 0) {
             if (kept) atomicAdd((unsigned long long *)&counters[0], (unsigned long long)kept);
             if (flagged) atomicAdd((unsigned long long *)&counters[1], (unsigned long long)flagged);
             if (dropped) atomicAdd((unsigned long long *)&counters[2], (unsigned long long)dropped);
         }
     }
     if (sumwt) {
-        // one atomic per wavefront when every lane with a group shares its plane
+        // one atomic per wavefront when every lane with a sample shares its plane
         unsigned long long has = __ballot(plane >= 0);
         int lead = has ? __shfl(plane, __ffsll((long long)has) - 1) : -1;
         bool uniform = __all(plane < 0 || plane == lead);
         if (uniform) {
             for (int p = 0; p < NPOL; ++p) {
                 double s = wave_sum(sw[p]);
-                if ((threadIdx.x & 63) == 0 && lead >= 0 && s != 0.0)
-                    atomicAdd(&sumwt[lead * NPOL + p], s);
+                if (lane == 0 && lead >= 0 && s != 0.0) atomicAdd(&sumwt[lead * NPOL + p], s);
             }
         } else if (plane >= 0) {
             for (int p = 0; p < NPOL; ++p)
@@ -227,97 +246,81 @@ __global__ __launch_bounds__(256) void k_presum(
 }
 
 // ---------------------------------------------------------------------------
-struct GridArgs {
+// Tile gridder.  One workgroup per chunk of (tile, group) pairs of one
+// 32 x 32 tile; thread t owns the four cells (x0 + t % 32, y0 + t / 32 + 8 j)
+// and accumulates Ct(o, t) phi(t) A_g for every group whose footprint covers
+// them, in registers.  A chunk that holds all of its tile's pairs writes the
+// tile with plain loads and stores; otherwise (and for the PSF's mirror
+// image) the flush is atomic.
+struct TileArgs {
     const GroupMeta *groups;
-    const int32_t *r_g0, *r_toff;
-    int64_t n_ranges, n_tasks;
+    const int32_t *tp_group, *chunk_start, *chunk_tile, *chunk_excl;
     const void *A;
     void *grid;
     CFView cf;
-    int32_t nx, ny;
+    int32_t nx, ny, ntx, nty;
     int64_t pol_stride;   // nx * ny
 };
 
 template <typename T, int ST, int NPOL, bool PO, bool PSF>
-__global__ __launch_bounds__(256) void k_grid(GridArgs a) {
-    const int lane = threadIdx.x & 63;
-    const int64_t t = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    if (t >= a.n_tasks) return;
-    // range of this task: largest r with r_toff[r] <= t
-    int64_t lo = 0, hi = a.n_ranges;
-    while (hi - lo > 1) {
-        int64_t mid = (lo + hi) >> 1;
-        if (a.r_toff[mid] <= t) lo = mid; else hi = mid;
-    }
-    const int chunk = (int)(t - a.r_toff[lo]);
-    const int32_t g0 = a.r_g0[lo], g1 = a.r_g0[lo + 1];
-    const GroupMeta *G = a.groups;
-    const int k = G[g0].k;
-    const int h = a.cf.h[k];
-    const int S = 2 * h + 1;
-    const int cls = chunk * 64 + lane;
-    const bool valid = cls < S * S;
-    const int rx = cls % S, ry = cls / S;
+__global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
+    const int c = blockIdx.x;
+    const int32_t s0 = a.chunk_start[c], s1 = a.chunk_start[c + 1];
+    const int32_t key = a.chunk_tile[c];
+    const bool excl = !PSF && a.chunk_excl[c];
+    const int tx = key % a.ntx;
+    const int rest = key / a.ntx;
+    const int ty = rest % a.nty;
+    const int P = rest / a.nty;
+    const int x = tx * kTile + (threadIdx.x & 31);
+    const int yb = ty * kTile + (threadIdx.x >> 5);
     const cpx<T> *Av = (const cpx<T> *)a.A;
+    cpx<T> acc[4][NPOL];
+    for (int j = 0; j < 4; ++j)
+        for (int p = 0; p < NPOL; ++p) acc[j][p] = {(T)0, (T)0};
+    int touched = 0;
+    for (int32_t i = s0; i < s1; ++i) {
+        const int32_t g = a.tp_group[i];
+        const GroupMeta gm = a.groups[g];
+        const int h = a.cf.h[gm.k];
+        const int S = 2 * h + 1;
+        const int dx = x - (gm.pu - h);
+        if (dx < 0 || dx >= S) continue;
+        const float sc = a.cf.scale[gm.fg * a.cf.n_w + gm.k];
+        cpx<T> av[NPOL];
+        for (int p = 0; p < NPOL; ++p) av[p] = Av[(int64_t)g * NPOL + p];
+        for (int j = 0; j < 4; ++j) {
+            const int dy = yb + 8 * j - (gm.pv - h);
+            if (dy < 0 || dy >= S) continue;
+            cpx<T> cv = CFElem<ST>::load(a.cf.table, gm.cf_off + dy * S + dx, sc);
+            if (gm.conj) cv.y = -cv.y;
+            if (PO) cv = cmul(cv, phasor<T>(gm, dx - h, dy - h, a.cf.O));
+            for (int p = 0; p < NPOL; ++p) cmac(acc[j][p], cv, av[p]);
+            touched |= 1 << j;
+        }
+    }
     T *grid = (T *)a.grid;
-
-    cpx<T> acc[NPOL];
-    for (int p = 0; p < NPOL; ++p) acc[p] = {(T)0, (T)0};
-    int64_t cur = -1, curbase = 0;
-    int cx = 0, cy = 0, dx = 0, dy = 0, tap = 0;
-    int64_t prev = -1;
-
-    auto flush = [&]() {
-        if (!valid || cur < 0) return;
+    for (int j = 0; j < 4; ++j) {
+        if (!(touched & (1 << j))) continue;
+        const int y = yb + 8 * j;
         for (int p = 0; p < NPOL; ++p) {
-            int64_t base = curbase + p * a.pol_stride;
-            T *q = grid + 2 * (base + (int64_t)cy * a.nx + cx);
+            const int64_t base = ((int64_t)P * NPOL + p) * a.pol_stride;
+            T *q = grid + 2 * (base + (int64_t)y * a.nx + x);
             if (PSF) {
-                T *m = grid + 2 * (base + (int64_t)(a.ny - cy) * a.nx + (a.nx - cx));
-                atomicAdd(q, (T)0.5 * acc[p].x);
-                atomicAdd(q + 1, (T)0.5 * acc[p].y);
-                atomicAdd(m, (T)0.5 * acc[p].x);
-                atomicAdd(m + 1, -(T)0.5 * acc[p].y);
+                T *m = grid + 2 * (base + (int64_t)(a.ny - y) * a.nx + (a.nx - x));
+                atomicAdd(q, (T)0.5 * acc[j][p].x);
+                atomicAdd(q + 1, (T)0.5 * acc[j][p].y);
+                atomicAdd(m, (T)0.5 * acc[j][p].x);
+                atomicAdd(m + 1, -(T)0.5 * acc[j][p].y);
+            } else if (excl) {
+                q[0] += acc[j][p].x;
+                q[1] += acc[j][p].y;
             } else {
-                atomicAdd(q, acc[p].x);
-                atomicAdd(q + 1, acc[p].y);
-            }
-        }
-    };
-
-    for (int32_t g = g0; g < g1; ++g) {
-        const GroupMeta gm = G[g];
-        if (gm.cell != prev) {
-            prev = gm.cell;
-            const int bx = gm.pu - h, by = gm.pv - h;
-            dx = rx - bx % S;
-            dx += dx < 0 ? S : 0;
-            dy = ry - by % S;
-            dy += dy < 0 ? S : 0;
-            const int64_t base = gm.cell - (int64_t)gm.pv * a.nx - gm.pu;
-            const int64_t nc = base + (int64_t)(by + dy) * a.nx + (bx + dx);
-            if (nc != cur) {
-                flush();
-                for (int p = 0; p < NPOL; ++p) acc[p] = {(T)0, (T)0};
-                cur = nc;
-                curbase = base;
-                cx = bx + dx;
-                cy = by + dy;
-            }
-            tap = dy * S + dx;
-        }
-        if (valid) {
-            const float sc = a.cf.scale[gm.fg * a.cf.n_w + k];
-            cpx<T> c = CFElem<ST>::load(a.cf.table, gm.cf_off + tap, sc);
-            if (gm.conj) c.y = -c.y;
-            if (PO) c = cmul(c, phasor<T>(gm, dx - h, dy - h, a.cf.O));
-            for (int p = 0; p < NPOL; ++p) {
-                const cpx<T> av = Av[(int64_t)g * NPOL + p];
-                cmac(acc[p], c, av);
+                atomicAdd(q, acc[j][p].x);
+                atomicAdd(q + 1, acc[j][p].y);
             }
         }
     }
-    flush();
 }
 
 // ---------------------------------------------------------------------------
@@ -388,25 +391,27 @@ static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / 
 template <typename T, int NPOL>
 static hipError_t presum_t(const lr_plan *P, const VisArgs &v, void *A, double *sumwt,
                            int64_t *counters, bool sums, hipStream_t s) {
-    int64_t n = P->n_groups > 0 ? P->n_groups : 1;
-    int64_t rest = P->n_pairs - P->n_kept;
-    if (rest > n) n = rest;
-    dim3 grd(nblk(n, 256)), blk(256);
+    dim3 grd(nblk(P->n_pairs, 256)), blk(256);
     const T *vis = (const T *)v.vis;
     const T *wt = (const T *)v.weight;
     long long *cnt = (long long *)counters;
+    if (sums) {
+        hipError_t e = launch_zero(A, (size_t)std::max<int64_t>(P->n_groups, 1) * NPOL *
+                                          sizeof(cpx<T>), s);
+        if (e != hipSuccess) return e;
+    }
     if (!sums)
-        hipLaunchKernelGGL((k_presum<T, NPOL, false, false>), grd, blk, 0, s, P->n_groups,
-                           P->n_kept, P->n_pairs, P->order, P->group_start, P->groups, vis,
-                           wt, (cpx<T> *)A, sumwt, cnt);
+        hipLaunchKernelGGL((k_presum<T, NPOL, false, false>), grd, blk, 0, s, P->n_kept,
+                           P->n_pairs, P->order, P->gidx, P->groups, vis, wt, (cpx<T> *)A,
+                           sumwt, cnt);
     else if (v.unit_vis)
-        hipLaunchKernelGGL((k_presum<T, NPOL, true, true>), grd, blk, 0, s, P->n_groups,
-                           P->n_kept, P->n_pairs, P->order, P->group_start, P->groups, vis,
-                           wt, (cpx<T> *)A, sumwt, cnt);
+        hipLaunchKernelGGL((k_presum<T, NPOL, true, true>), grd, blk, 0, s, P->n_kept,
+                           P->n_pairs, P->order, P->gidx, P->groups, vis, wt, (cpx<T> *)A,
+                           sumwt, cnt);
     else
-        hipLaunchKernelGGL((k_presum<T, NPOL, false, true>), grd, blk, 0, s, P->n_groups,
-                           P->n_kept, P->n_pairs, P->order, P->group_start, P->groups, vis,
-                           wt, (cpx<T> *)A, sumwt, cnt);
+        hipLaunchKernelGGL((k_presum<T, NPOL, false, true>), grd, blk, 0, s, P->n_kept,
+                           P->n_pairs, P->order, P->gidx, P->groups, vis, wt, (cpx<T> *)A,
+                           sumwt, cnt);
     return hipGetLastError();
 }
 
@@ -436,39 +441,43 @@ hipError_t launch_counts(const lr_plan *P, const void *weight, int precision, in
 }
 
 template <typename T, int ST, int NPOL>
-static hipError_t grid_t(const GridArgs &ga, bool po, bool psf, hipStream_t s) {
-    dim3 grd(nblk(ga.n_tasks, 4)), blk(256);
+static hipError_t grid_t(const TileArgs &ta, int64_t n_chunks, bool po, bool psf,
+                         hipStream_t s) {
+    dim3 grd((unsigned)n_chunks), blk(256);
     if (po) {
-        if (psf) hipLaunchKernelGGL((k_grid<T, ST, NPOL, true, true>), grd, blk, 0, s, ga);
-        else hipLaunchKernelGGL((k_grid<T, ST, NPOL, true, false>), grd, blk, 0, s, ga);
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, true>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, false>), grd, blk, 0, s, ta);
     } else {
-        if (psf) hipLaunchKernelGGL((k_grid<T, ST, NPOL, false, true>), grd, blk, 0, s, ga);
-        else hipLaunchKernelGGL((k_grid<T, ST, NPOL, false, false>), grd, blk, 0, s, ga);
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, true>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false>), grd, blk, 0, s, ta);
     }
     return hipGetLastError();
 }
 
 template <typename T, int ST>
-static hipError_t grid_np(const GridArgs &ga, int npol, bool po, bool psf, hipStream_t s) {
+static hipError_t grid_np(const TileArgs &ta, int64_t n_chunks, int npol, bool po, bool psf,
+                          hipStream_t s) {
     switch (npol) {
-        case 1: return grid_t<T, ST, 1>(ga, po, psf, s);
-        case 2: return grid_t<T, ST, 2>(ga, po, psf, s);
-        default: return grid_t<T, ST, 4>(ga, po, psf, s);
+        case 1: return grid_t<T, ST, 1>(ta, n_chunks, po, psf, s);
+        case 2: return grid_t<T, ST, 2>(ta, n_chunks, po, psf, s);
+        default: return grid_t<T, ST, 4>(ta, n_chunks, po, psf, s);
     }
 }
 
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
                        int precision, int32_t npol, int32_t nx, int32_t ny, int32_t psf,
                        hipStream_t s) {
-    if (P->n_tasks == 0) return hipSuccess;
-    GridArgs ga{P->groups, P->r_g0, P->r_toff, P->n_ranges, P->n_tasks, A, grid, cf, nx, ny,
+    if (P->n_chunks == 0) return hipSuccess;
+    TileArgs ta{P->groups, P->tp_group, P->chunk_start, P->chunk_tile, P->chunk_excl, A, grid,
+                cf, nx, ny, (nx + kTile - 1) / kTile, (ny + kTile - 1) / kTile,
                 (int64_t)nx * ny};
     bool po = P->po != 0;
+    int64_t nc = P->n_chunks;
     switch (precision) {
-        case LR_F64: return grid_np<double, LR_F64>(ga, npol, po, psf, s);
-        case LR_F32: return grid_np<float, LR_F32>(ga, npol, po, psf, s);
-        case LR_F32_CF16: return grid_np<float, LR_F32_CF16>(ga, npol, po, psf, s);
-        default: return grid_np<float, LR_F32_CFBF16>(ga, npol, po, psf, s);
+        case LR_F64: return grid_np<double, LR_F64>(ta, nc, npol, po, psf, s);
+        case LR_F32: return grid_np<float, LR_F32>(ta, nc, npol, po, psf, s);
+        case LR_F32_CF16: return grid_np<float, LR_F32_CF16>(ta, nc, npol, po, psf, s);
+        default: return grid_np<float, LR_F32_CFBF16>(ta, nc, npol, po, psf, s);
     }
 }
 

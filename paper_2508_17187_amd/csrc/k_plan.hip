@@ -199,27 +199,86 @@ __global__ void k_group_meta(const int32_t *vals, const int32_t *flags, const in
     groups[gi] = gm;
 }
 
+// The exclusive scan counts a group's own start for every later pair of the
+// group; turn it into the group index of every sorted position.
+__global__ void k_group_index(int32_t *gidx, const int32_t *flags, int64_t n_kept) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_kept) gidx[i] += flags[i] - 1;
+}
+
 __global__ void k_group_end(int32_t *group_start, int64_t n_groups, int64_t n_kept) {
     if (threadIdx.x == 0) group_start[n_groups] = (int32_t)n_kept;
 }
 
-// Ranges: runs of at most `per` groups of one w-plane.
-__global__ void k_range_flags(const GroupMeta *groups, int64_t n_groups, int32_t per,
-                              int32_t *flags) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_groups) return;
-    flags[i] = (i == 0 || (i % per) == 0 || groups[i].k != groups[i - 1].k) ? 1 : 0;
+// ---- tiles of the gridder ----------------------------------------------------
+// Each group's footprint is cut by the 32 x 32 cell tiles it overlaps; the
+// (tile, group) pairs are sorted by tile and split into chunks of at most
+// `per` pairs, one workgroup each.
+__device__ __forceinline__ void tile_span(const GroupMeta &gm, int h, int &tx0, int &tx1,
+                                          int &ty0, int &ty1) {
+    tx0 = (gm.pu - h) / kTile;
+    tx1 = (gm.pu + h) / kTile;
+    ty0 = (gm.pv - h) / kTile;
+    ty1 = (gm.pv + h) / kTile;
 }
 
-__global__ void k_range_build(const GroupMeta *groups, const int32_t *flags,
-                              const int32_t *ridx, int64_t n_groups, const int32_t *h,
-                              int32_t *r_g0, int32_t *r_nch) {
+__global__ void k_tile_count(const GroupMeta *groups, int64_t n_groups, const int32_t *h,
+                             int32_t *counts) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_groups || !flags[i]) return;
-    int32_t r = ridx[i];
-    r_g0[r] = (int32_t)i;
-    int32_t S = 2 * h[groups[i].k] + 1;
-    r_nch[r] = (S * S + 63) / 64;
+    if (i >= n_groups) return;
+    GroupMeta gm = groups[i];
+    int tx0, tx1, ty0, ty1;
+    tile_span(gm, h[gm.k], tx0, tx1, ty0, ty1);
+    counts[i] = (tx1 - tx0 + 1) * (ty1 - ty0 + 1);
+}
+
+__global__ void k_tile_fill(const GroupMeta *groups, int64_t n_groups, const int32_t *h,
+                            const int32_t *off, int32_t ntx, int32_t nty, uint32_t *keys,
+                            int32_t *vals) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_groups) return;
+    GroupMeta gm = groups[i];
+    int tx0, tx1, ty0, ty1;
+    tile_span(gm, h[gm.k], tx0, tx1, ty0, ty1);
+    int32_t o = off[i];
+    for (int ty = ty0; ty <= ty1; ++ty)
+        for (int tx = tx0; tx <= tx1; ++tx) {
+            keys[o] = (uint32_t)(((int64_t)gm.plane * nty + ty) * ntx + tx);
+            vals[o] = (int32_t)i;
+            ++o;
+        }
+}
+
+__global__ void k_chunk_flags(const uint32_t *keys, int64_t n, int32_t per, int32_t *flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    flags[i] = (i == 0 || keys[i] != keys[i - 1] || (i % per) == 0) ? 1 : 0;
+}
+
+__global__ void k_chunk_build(const uint32_t *keys, const int32_t *flags, const int32_t *cidx,
+                              int64_t n, int32_t *chunk_start, int32_t *chunk_tile) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || !flags[i]) return;
+    int32_t c = cidx[i];
+    chunk_start[c] = (int32_t)i;
+    chunk_tile[c] = (int32_t)keys[i];
+}
+
+// A chunk that holds all of its tile's pairs owns the tile: it may update
+// the grid with plain loads and stores instead of atomics.
+__global__ void k_chunk_excl(const uint32_t *keys, int32_t *chunk_start, int64_t n_chunks,
+                             int64_t n, int32_t *chunk_excl) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    int64_t s = chunk_start[c];
+    int64_t e = (c + 1 < n_chunks) ? chunk_start[c + 1] : n;
+    bool first = (s == 0) || keys[s - 1] != keys[s];
+    bool last = (e == n) || keys[e] != keys[e - 1];
+    chunk_excl[c] = (first && last) ? 1 : 0;
+}
+
+__global__ void k_chunk_end(int32_t *chunk_start, int64_t n_chunks, int64_t n) {
+    if (threadIdx.x == 0) chunk_start[n_chunks] = (int32_t)n;
 }
 
 __global__ void k_taps(const GroupMeta *groups, int64_t n_groups, const int32_t *h,
@@ -234,53 +293,54 @@ __global__ void k_taps(const GroupMeta *groups, int64_t n_groups, const int32_t 
     if ((threadIdx.x & 63) == 0 && t) atomicAdd(out, t);
 }
 
-__global__ void k_range_end(int32_t *r_g0, int32_t *r_toff, const int32_t *r_nch,
-                            int64_t n_ranges, int64_t n_groups) {
-    if (threadIdx.x == 0) {
-        r_g0[n_ranges] = (int32_t)n_groups;
-        r_toff[n_ranges] = r_toff[n_ranges - 1] + r_nch[n_ranges - 1];
-    }
-}
-
 // ---------------------------------------------------------------------------
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-size_t sort_temp_bytes(int64_t n) {
-    size_t bytes = 0;
+size_t sort_temp_bytes(int64_t n, int64_t n_tp) {
+    size_t bytes = 0, b2 = 0, sb = 0, sb2 = 0;
     rocprim::radix_sort_pairs((void *)nullptr, bytes, (uint64_t *)nullptr,
                               (uint64_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
                               (size_t)n, 0, 64);
-    size_t sb = 0;
+    rocprim::radix_sort_pairs((void *)nullptr, b2, (uint32_t *)nullptr,
+                              (uint32_t *)nullptr, (int32_t *)nullptr, (int32_t *)nullptr,
+                              (size_t)n_tp, 0, 32);
     rocprim::exclusive_scan((void *)nullptr, sb, (int32_t *)nullptr, (int32_t *)nullptr,
                             (int32_t)0, (size_t)n, rocprim::plus<int32_t>());
-    return std::max(bytes, sb);
+    rocprim::exclusive_scan((void *)nullptr, sb2, (int32_t *)nullptr, (int32_t *)nullptr,
+                            (int32_t)0, (size_t)n_tp, rocprim::plus<int32_t>());
+    return std::max(std::max(bytes, b2), std::max(sb, sb2));
 }
 
-PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t per, int64_t n_segments) {
+int64_t max_tiles_per_group(int32_t h_max) {
+    int64_t span = (2 * (int64_t)h_max + kTile - 1) / kTile + 1;
+    return span * span;
+}
+
+PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max) {
     PlanLayout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
     int64_t n = std::max<int64_t>(n_pairs, 1);
+    int64_t ntp = n * max_tiles_per_group(h_max);
     L.chan = take(sizeof(ChanConst) * (nchan > 0 ? nchan : 1));
-    // ranges: one per `per` groups plus one per change of w-plane in the
-    // sorted order (at most one per (plane, A-term group, w-plane) segment)
-    int64_t nr = n / per + n_segments + 2;
     L.order = take(sizeof(int32_t) * n);
     L.gidx = take(sizeof(int32_t) * n);
     L.group_start = take(sizeof(int32_t) * (n + 1));
     L.groups = take(sizeof(GroupMeta) * n);
-    L.r_g0 = take(sizeof(int32_t) * (nr + 1));
-    L.r_toff = take(sizeof(int32_t) * (nr + 1));
+    L.tp_group = take(sizeof(int32_t) * ntp);
+    L.chunk_start = take(sizeof(int32_t) * (ntp + 1));
+    L.chunk_tile = take(sizeof(int32_t) * ntp);
+    L.chunk_excl = take(sizeof(int32_t) * ntp);
     L.persistent = off;
     // transient
-    L.keys_a = take(sizeof(uint64_t) * n);
-    L.keys_b = take(sizeof(uint64_t) * n);
-    L.vals_a = take(sizeof(int32_t) * n);
-    L.flags = take(sizeof(int32_t) * n);
-    L.r_nch = take(sizeof(int32_t) * (nr + 1));
+    L.keys_a = take(sizeof(uint64_t) * std::max(n, ntp));
+    L.keys_b = take(sizeof(uint64_t) * std::max(n, ntp));
+    L.vals_a = take(sizeof(int32_t) * std::max(n, ntp));
+    L.flags = take(sizeof(int32_t) * std::max(n, ntp));
+    L.scan = take(sizeof(int32_t) * std::max(n, ntp));
     L.counter = take(64);
-    L.temp = take(sort_temp_bytes(n));
-    L.max_ranges = nr;
+    L.temp = take(sort_temp_bytes(n, ntp));
+    L.max_tp = ntp;
     L.total = off;
     return L;
 }
@@ -301,14 +361,16 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     int32_t *gidx = (int32_t *)(buf + L.gidx);
     unsigned long long *counter = (unsigned long long *)(buf + L.counter);
     void *temp = buf + L.temp;
-    size_t temp_bytes = sort_temp_bytes(n);
+    size_t temp_bytes = sort_temp_bytes(n, L.max_tp);
     P->order = order;
     P->gidx = gidx;
     P->group_start = (int32_t *)(buf + L.group_start);
     P->groups = (GroupMeta *)(buf + L.groups);
-    P->r_g0 = (int32_t *)(buf + L.r_g0);
-    P->r_toff = (int32_t *)(buf + L.r_toff);
-    P->n_kept = P->n_groups = P->n_ranges = P->n_tasks = 0;
+    P->tp_group = (int32_t *)(buf + L.tp_group);
+    P->chunk_start = (int32_t *)(buf + L.chunk_start);
+    P->chunk_tile = (int32_t *)(buf + L.chunk_tile);
+    P->chunk_excl = (int32_t *)(buf + L.chunk_excl);
+    P->n_kept = P->n_groups = P->n_tile_pairs = P->n_chunks = P->taps = 0;
     if (n == 0) return hipSuccess;
 
     if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
@@ -340,37 +402,54 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
                        du_dl, dv_dm, P->group_start, P->groups);
     hipLaunchKernelGGL(k_group_end, dim3(1), dim3(64), 0, s, P->group_start, P->n_groups,
                        (int64_t)nk);
+    hipLaunchKernelGGL(k_group_index, dim3(blocks(nk, 256)), dim3(256), 0, s, gidx, flags,
+                       (int64_t)nk);
     if ((e = hipGetLastError()) != hipSuccess) return e;
 
-    // wavefront tasks of the gridder
-    int32_t *r_nch = (int32_t *)(buf + L.r_nch);
-    hipLaunchKernelGGL(k_range_flags, dim3(blocks(P->n_groups, 256)), dim3(256), 0, s,
-                       P->groups, P->n_groups, per, flags);
-    e = rocprim::exclusive_scan(temp, temp_bytes, flags, (int32_t *)keys_a, (int32_t)0,
-                                (size_t)P->n_groups, rocprim::plus<int32_t>(), s);
+    // (tile, group) pairs and chunks of the gridder
+    int32_t *scan = (int32_t *)(buf + L.scan);
+    uint32_t *tk_a = (uint32_t *)keys_a, *tk_b = (uint32_t *)keys_b;
+    int64_t ng = P->n_groups;
+    hipLaunchKernelGGL(k_tile_count, dim3(blocks(ng, 256)), dim3(256), 0, s, P->groups, ng,
+                       cf.h, flags);
+    e = rocprim::exclusive_scan(temp, temp_bytes, flags, scan, (int32_t)0, (size_t)ng,
+                                rocprim::plus<int32_t>(), s);
     if (e != hipSuccess) return e;
-    int32_t *ridx = (int32_t *)keys_a;
-    (void)hipMemcpyAsync(&tail[0], ridx + P->n_groups - 1, 4, hipMemcpyDeviceToHost, s);
-    (void)hipMemcpyAsync(&tail[1], flags + P->n_groups - 1, 4, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&tail[0], scan + ng - 1, 4, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&tail[1], flags + ng - 1, 4, hipMemcpyDeviceToHost, s);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    P->n_ranges = (int64_t)tail[0] + tail[1];
-    if (P->n_ranges > L.max_ranges) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_range_build, dim3(blocks(P->n_groups, 256)), dim3(256), 0, s,
-                       P->groups, flags, ridx, P->n_groups, cf.h, P->r_g0, r_nch);
-    e = rocprim::exclusive_scan(temp, temp_bytes, r_nch, P->r_toff, (int32_t)0,
-                                (size_t)P->n_ranges, rocprim::plus<int32_t>(), s);
+    int64_t ntp = (int64_t)tail[0] + tail[1];
+    if (ntp > L.max_tp) return hipErrorInvalidValue;
+    int32_t ntx = (g.nx + kTile - 1) / kTile, nty = (g.ny + kTile - 1) / kTile;
+    hipLaunchKernelGGL(k_tile_fill, dim3(blocks(ng, 256)), dim3(256), 0, s, P->groups, ng,
+                       cf.h, scan, ntx, nty, tk_a, vals_a);
+    int end_bit = 1;
+    while (end_bit < 32 && ((int64_t)1 << end_bit) < (int64_t)g.nplane * ntx * nty) ++end_bit;
+    e = rocprim::radix_sort_pairs(temp, temp_bytes, tk_a, tk_b, vals_a, P->tp_group,
+                                  (size_t)ntp, 0, end_bit, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_range_end, dim3(1), dim3(64), 0, s, P->r_g0, P->r_toff, r_nch,
-                       P->n_ranges, P->n_groups);
+    hipLaunchKernelGGL(k_chunk_flags, dim3(blocks(ntp, 256)), dim3(256), 0, s, tk_b, ntp, per,
+                       flags);
+    e = rocprim::exclusive_scan(temp, temp_bytes, flags, scan, (int32_t)0, (size_t)ntp,
+                                rocprim::plus<int32_t>(), s);
+    if (e != hipSuccess) return e;
+    (void)hipMemcpyAsync(&tail[0], scan + ntp - 1, 4, hipMemcpyDeviceToHost, s);
+    (void)hipMemcpyAsync(&tail[1], flags + ntp - 1, 4, hipMemcpyDeviceToHost, s);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    int64_t nch = (int64_t)tail[0] + tail[1];
+    hipLaunchKernelGGL(k_chunk_build, dim3(blocks(ntp, 256)), dim3(256), 0, s, tk_b, flags,
+                       scan, ntp, P->chunk_start, P->chunk_tile);
+    hipLaunchKernelGGL(k_chunk_excl, dim3(blocks(nch, 256)), dim3(256), 0, s, tk_b,
+                       P->chunk_start, nch, ntp, P->chunk_excl);
+    hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(64), 0, s, P->chunk_start, nch, ntp);
     if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_taps, dim3(blocks(P->n_groups, 256)), dim3(256), 0, s, P->groups,
-                       P->n_groups, cf.h, counter);
-    int32_t nt = 0;
+    hipLaunchKernelGGL(k_taps, dim3(blocks(ng, 256)), dim3(256), 0, s, P->groups, ng, cf.h,
+                       counter);
     unsigned long long taps = 0;
-    (void)hipMemcpyAsync(&nt, P->r_toff + P->n_ranges, 4, hipMemcpyDeviceToHost, s);
     (void)hipMemcpyAsync(&taps, counter, 8, hipMemcpyDeviceToHost, s);
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
-    P->n_tasks = nt;
+    P->n_tile_pairs = ntp;
+    P->n_chunks = nch;
     P->taps = (int64_t)taps;
     return hipGetLastError();
 }

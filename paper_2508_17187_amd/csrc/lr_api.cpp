@@ -261,14 +261,17 @@ MapGeom map_geom(const lr_cf *cf, int32_t nchan, int psf) {
     return m;
 }
 
-int32_t range_groups() {
+// (tile, group) pairs per gridder workgroup
+int32_t chunk_pairs() {
     static int32_t v = [] {
-        const char *e = getenv("LR_GRID_RANGE");
+        const char *e = getenv("LR_TILE_CHUNK");
         int x = e ? atoi(e) : 0;
-        return x >= 1 && x <= (1 << 20) ? x : 128;
+        return x >= 1 && x <= (1 << 20) ? x : 64;
     }();
     return v;
 }
+
+int32_t h_max_of(const lr_cf *cf) { return *std::max_element(cf->h.begin(), cf->h.end()); }
 
 KeyLayout key_layout(const lr_cf *cf, const lr_vis *v, bool po, int32_t &merged) {
     KeyLayout k;
@@ -295,12 +298,8 @@ KeyLayout key_layout(const lr_cf *cf, const lr_vis *v, bool po, int32_t &merged)
     return k;
 }
 
-int64_t n_segments(const lr_cf *cf) {
-    return (int64_t)cf->grid.nplane * cf->spec.n_fg * cf->spec.n_w;
-}
-
 size_t plan_total(const lr_cf *cf, const lr_vis *v) {
-    return plan_layout((int64_t)v->nrow * v->nchan, v->nchan, range_groups(), n_segments(cf)).total;
+    return plan_layout((int64_t)v->nrow * v->nchan, v->nchan, h_max_of(cf)).total;
 }
 
 lr_status plan_matches(const lr_plan *P, const lr_cf *cf, const lr_vis *v, int psf) {
@@ -323,7 +322,7 @@ lr_status plan_matches(const lr_plan *P, const lr_cf *cf, const lr_vis *v, int p
 lr_status build_plan(const lr_cf *cf, const lr_vis *v, int psf, void *buf, size_t bytes,
                      hipStream_t s, lr_plan *P) {
     int64_t n_pairs = (int64_t)v->nrow * v->nchan;
-    PlanLayout L = plan_layout(n_pairs, v->nchan, range_groups(), n_segments(cf));
+    PlanLayout L = plan_layout(n_pairs, v->nchan, h_max_of(cf));
     if (!buf && L.total) return fail(LR_E_ARG, "plan buffer is NULL");
     if (bytes < L.total) return fail(LR_E_WORKSPACE, "plan needs %zu bytes, got %zu", L.total, bytes);
     bool po = v->ant1 != nullptr;
@@ -349,9 +348,9 @@ lr_status build_plan(const lr_cf *cf, const lr_vis *v, int psf, void *buf, size_
     double du_dl = 1.0 / ((double)cf->grid.nx * cf->grid.cell_l);
     double dv_dm = 1.0 / ((double)cf->grid.ny * cf->grid.cell_m);
     e = build_plan_device(P, b, L, v->uvw, d_cc, g, kl, view_of(cf), v->ant1, v->ant2,
-                          v->nant, v->ant_dlm, du_dl, dv_dm, range_groups(), s);
-    if (e == hipErrorInvalidValue && P->n_ranges > L.max_ranges)
-        return fail(LR_E_RANGE, "plan range table overflow");
+                          v->nant, v->ant_dlm, du_dl, dv_dm, chunk_pairs(), s);
+    if (e == hipErrorInvalidValue)
+        return fail(LR_E_RANGE, "plan tile table overflow");
     if (e != hipSuccess) return dev_fail(e, "plan build");
     return LR_OK;
 }
@@ -412,8 +411,7 @@ size_t lr_workspace_bytes(int op, const lr_cf_spec *spec, const lr_grid_spec *gr
     if (op == LR_OP_CF_BUILD) return cf_work_bytes(G.M, spec->oversample, G.hmax);
     if (!vis) { fail(LR_E_ARG, "vis descriptor is NULL"); return 0; }
     int64_t n_pairs = (int64_t)vis->nrow * vis->nchan;
-    int64_t n_segs = (int64_t)grid->nplane * spec->n_fg * spec->n_w;
-    size_t plan = vis->plan ? 0 : al256(plan_layout(n_pairs, vis->nchan, range_groups(), n_segs).total);
+    size_t plan = vis->plan ? 0 : al256(plan_layout(n_pairs, vis->nchan, G.hmax).total);
     int64_t n_groups = vis->plan ? vis->plan->n_groups : n_pairs;
     size_t per = 0;
     if (op == LR_OP_GRID || op == LR_OP_PSF || op == LR_OP_DEGRID)

@@ -15,6 +15,7 @@ namespace lr {
 
 constexpr double kCLight = 299792458.0;
 constexpr int kMaxChanPerUpload = 48;
+constexpr int kTile = 32;          // gridder tile side (cells)
 
 // ---------------------------------------------------------------------------
 // Per-channel constants formed on the host in FP64 (no contraction).
@@ -122,13 +123,15 @@ struct lr_plan {
     std::vector<double> freq;
     std::vector<int32_t> chan_plane, chan_fg;
     // counts
-    int64_t n_pairs, n_kept, n_groups, n_ranges, n_tasks, taps;
+    int64_t n_pairs, n_kept, n_groups, n_tile_pairs, n_chunks, taps;
     // device arrays inside the caller's buffer
     int32_t *order;            // [n_pairs] pair ids; kept (sorted) first; bit 30 set = skipped channel
     int32_t *gidx;             // [n_kept] group of each sorted kept pair
     int32_t *group_start;      // [n_groups + 1]
     lr::GroupMeta *groups;     // [n_groups]
-    int32_t *r_g0;             // [n_ranges + 1] first group of each gridder range
-    int32_t *r_toff;           // [n_ranges + 1] first wavefront task of each range
+    int32_t *tp_group;         // [n_tile_pairs] group of each (tile, group) pair, by tile
+    int32_t *chunk_start;      // [n_chunks + 1] first pair of each gridder chunk
+    int32_t *chunk_tile;       // [n_chunks] tile id: (plane * nty + ty) * ntx + tx
+    int32_t *chunk_excl;       // [n_chunks] 1 when the chunk holds all pairs of its tile
     size_t bytes_used;
 };

@@ -15,9 +15,10 @@ struct KeyLayout {
 };
 
 struct PlanLayout {
-    size_t chan, order, gidx, group_start, groups, r_g0, r_toff, persistent;
-    size_t keys_a, keys_b, vals_a, flags, r_nch, counter, temp;
-    int64_t max_ranges;
+    size_t chan, order, gidx, group_start, groups, tp_group, chunk_start, chunk_tile,
+        chunk_excl, persistent;
+    size_t keys_a, keys_b, vals_a, flags, scan, counter, temp;
+    int64_t max_tp;
     size_t total;
 };
 
@@ -26,8 +27,9 @@ hipError_t upload_words(const void *src, size_t bytes, void *d, hipStream_t s);
 hipError_t launch_debug_map(int64_t nrow, int32_t nchan, const double *uvw,
                             const std::vector<ChanConst> &cc, const MapGeom &g, int32_t *out,
                             hipStream_t s);
-size_t sort_temp_bytes(int64_t n);
-PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t per, int64_t n_segments);
+size_t sort_temp_bytes(int64_t n, int64_t n_tp);
+int64_t max_tiles_per_group(int32_t h_max);
+PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max);
 hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const double *uvw,
                              const ChanConst *d_cc, const MapGeom &g, const KeyLayout &kl,
                              const CFView &cf, const int32_t *ant1, const int32_t *ant2,

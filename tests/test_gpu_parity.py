@@ -141,11 +141,15 @@ def test_cf_table_matches_oracle(awp, form):
     if form != "f32":
         assert np.array_equal(cf.scale_exponents(), plane_scale_exponents(ocf))
     diff = np.abs(got - q)
-    mism = diff > 0
-    # identical except where the FP64 values straddle a rounding tie
-    assert mism.mean() < 1e-3
+    # identical except where the two FP64 tables (which differ by <5e-13 of
+    # the peak) straddle a rounding boundary of the storage format
+    # (rounding noise of the FP64 tables, ~1e-19 here, is itself stored
+    # faithfully by f32 / bf16, so only differences above it count)
+    big = np.abs(ref) > 1e-6 * scale
+    assert (diff[big] > 1e-13 * scale).mean() < 1e-3
     ulp = {"f32": 2.0 ** -23, "f16cf": 2.0 ** -10, "bf16cf": 2.0 ** -7}[form]
-    assert np.all(diff <= ulp * np.maximum(np.abs(ref), 2.0 ** -24 * scale) * 1.01 + 1e-300)
+    sub = 2.0 ** -24 * scale if form == "f16cf" else 0.0     # fp16 subnormal step
+    assert np.all(diff <= ulp * np.abs(ref) * 1.01 + 2 * sub + 1e-12 * scale)
 
 
 # --- gridding, degridding, PSF --------------------------------------------------------
