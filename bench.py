@@ -103,10 +103,36 @@ def run_form(wl, form, steps, warmup, ev):
     for pr in pairs:
         ev.free(*pr[0])
         ev.free(*pr[1])
+    # the same step captured once in a HIP graph and replayed: removes the
+    # host-side launch overhead of the eager loop (no allocation, memset or
+    # synchronisation happens inside the captured calls)
+    dt_graph = None
+    try:
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        dt_graph = time.perf_counter() - t0
+    except Exception as e:          # report eager numbers only
+        log("  graph capture unavailable:", repr(e))
     n = wl.nsamples
+    best = dt if dt_graph is None else min(dt, dt_graph)
     res = {
-        "vis_per_s": n * steps / dt,
-        "ms_per_step": 1e3 * dt / steps,
+        "vis_per_s": n * steps / best,
+        "ms_per_step": 1e3 * best / steps,
+        "ms_per_step_eager": 1e3 * dt / steps,
+        "ms_per_step_graph": None if dt_graph is None else 1e3 * dt_graph / steps,
         "grid_kernel_ms": sum(kg) / len(kg),
         "degrid_kernel_ms": sum(kd) / len(kd),
         "cf_build_ms": 1e3 * t_cf,
@@ -116,6 +142,129 @@ def run_form(wl, form, steps, warmup, ev):
         "taps": info["taps"],
     }
     return res, g, vout.vis
+
+
+ELEM = {"f64": 16, "f32": 8, "f16cf": 4, "bf16cf": 4}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grid_tile_wproj2048_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2508_17187_amd", "csrc", "k_grid.hip")
+
+
+def gridder_roofline(wl, form, r):
+    """Roofline of the gridder kernel (one launch grids all groups).
+
+    Algorithmic flops: 8 per complex multiply-add, npol per kernel tap of
+    every group.  Algorithmic bytes: the presummed group values (npol
+    complex), every group's S x S sub-kernel once, the grid written once.
+    The binding roof is the one with the longer time at peak."""
+    import hashlib
+    npol = wl.grid.npol
+    cplx = 16 if form == "f64" else 8
+    flops = 8.0 * npol * r["taps"]
+    grid_bytes = wl.grid.nplane * npol * wl.grid.nx * wl.grid.ny * cplx
+    bytes_ = r["n_groups"] * npol * cplx + r["taps"] * ELEM[form] + grid_bytes
+    t = r["grid_kernel_ms"] * 1e-3
+    hbm = bytes_ / HBM_PEAK >= flops / PEAK[form]
+    traffic = None
+    try:
+        tr = json.load(open(TRAFFIC_FILE))
+        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+        if tr.get("kernel_source_sha256") == sha and tr.get("form") == form:
+            traffic = tr["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    if hbm:
+        return {"bound": "hbm", "kernel": "k_grid_tile (gridder)", "achieved": bytes_ / t / 1e9,
+                "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": bytes_ / t / HBM_PEAK,
+                "traffic": traffic, "algorithmic_bytes_per_launch": bytes_,
+                "algorithmic_flops_per_launch": flops,
+                "alu_frac": flops / t / PEAK[form], "kernel_ms": r["grid_kernel_ms"]}
+    return {"bound": "alu", "kernel": "k_grid_tile (gridder)", "achieved": flops / t / 1e12,
+            "peak": PEAK[form] / 1e12, "unit": "TFLOP/s", "frac": flops / t / PEAK[form],
+            "traffic": traffic, "algorithmic_bytes_per_launch": bytes_,
+            "algorithmic_flops_per_launch": flops, "hbm_frac": bytes_ / t / HBM_PEAK,
+            "kernel_ms": r["grid_kernel_ms"]}
+
+
+def serving_bench(n_jobs=256, rate=20.0, budget_gb=64.0, slots=4, form="f32"):
+    """Poisson stream of grid / degrid jobs (configuration 4): visibility
+    counts log-uniform in [1e4, 2e7] (4 pols, one 3 GHz channel), grids of
+    512^2 .. 4096^2 x 4 at 0.2 arcsec, 1 .. 64 w-planes (w_max fixed from the
+    36 km layout at 4 GHz), 5-source skies.  Jobs are submitted at their
+    arrival times to a continuous-batching server; returns its stats."""
+    import math
+    import threading
+    import numpy as np
+    import torch
+    import synth
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import serving as S
+    from paper_2508_17187_amd import workload as W
+    p = lr.PRECISIONS[form]
+    specs = synth.config4_jobs(n_jobs, rate)
+    enu = synth.antenna_layout(27, 36000.0, seed=1004)
+    full, _, _, nbl = synth.uvw_tracks(enu, 480, 60.0, 30.0)
+    w_max = float(np.max(np.abs(full[:, 2])) * 4.0e9 / synth.C_LIGHT)
+    cell = 0.2 * synth.ARCSEC
+    rng = np.random.default_rng(4005)
+    models = {}
+    jobs = []
+    for sp in specs:
+        nrow = max(1, math.ceil(sp.n_samples / 4))
+        n_time = math.ceil(nrow / nbl)
+        uvw, _, _, _ = synth.uvw_tracks(enu, n_time, 2.0, 30.0)
+        uvw = np.ascontiguousarray(uvw[:nrow])
+        freq = np.array([3.0e9])
+        sky = synth.random_point_sky(5, seed=sp.seed, half_width_deg=0.05)
+        vis = synth.dft_visibilities(uvw, freq, sky, 4, device="cuda").astype(np.complex64)
+        wt = np.ones(vis.shape, np.float32)
+        N = sp.n_grid
+        gs = lr.GridSpec(N, N, 4, 1, cell, cell)
+        if sp.n_w == 1:
+            cs = dict(terms=1, oversample=100, ps_support=7, n_w=1, w_max=0.0, h_min=3,
+                      h_max=3, n_fg=1, fg_hz=np.array([3e9]), dish_m=25.0, screen_m=0,
+                      storage=p)
+            cfb = S.cf_bytes(1, 3, 3, 100)
+        else:
+            cs = dict(terms=3, oversample=20, ps_support=7, n_w=sp.n_w, w_max=w_max, h_min=8,
+                      h_max=32, n_fg=1, fg_hz=np.array([3e9]), dish_m=25.0, screen_m=0,
+                      storage=p)
+            cfb = S.cf_bytes(sp.n_w, 8, 32, 20)
+        g = None
+        if sp.op == "degrid":
+            if N not in models:
+                models[N] = (rng.standard_normal((1, 4, N, N), np.float32)
+                             + 1j * rng.standard_normal((1, 4, N, N), np.float32)
+                             ).astype(np.complex64)
+            g = models[N]
+        payload = dict(grid_spec=gs, cf_spec=cs, uvw=uvw, freq=freq,
+                       chan_plane=np.zeros(1, np.int32), vis=vis, weight=wt, grid=g)
+        jobs.append(S.Job(sp.job_id, sp.op, (N, sp.n_w), S.job_bytes(nrow, 1, 4, N) +
+                          600 * nrow, cfb, payload=payload, n_vis=vis.size,
+                          t_arrival=sp.arrival_s))
+    arrivals = [j.t_arrival for j in jobs]
+    exe = S.GPUExecutor(slots, p)
+    srv = S.Server(exe, hbm_budget=int(budget_gb * (1 << 30)), n_slots=slots)
+    t0 = time.perf_counter()
+
+    def submit_all():
+        for j, ta in zip(jobs, arrivals):
+            d = t0 + ta - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            srv.submit(j)
+
+    th = threading.Thread(target=submit_all)
+    th.start()
+    th.join()
+    srv.drain(timeout=900)
+    st = srv.stats()
+    srv.close()
+    st["n_jobs"] = n_jobs
+    st["arrival_rate_hz"] = rate
+    st["slots"] = slots
+    st["form"] = form
+    st["total_vis"] = int(sum(j.n_vis for j in jobs))
+    return st
 
 
 def cpu_baseline(wl, seconds=15.0):
@@ -164,6 +313,10 @@ def main():
                     help="forms measured beside the headline one")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--serving-jobs", type=int, default=256,
+                    help="jobs in the serving stream (0 = skip it)")
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="run one 1 GiB device copy first (scale of the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would "
@@ -174,6 +327,12 @@ def main():
     import torch
     import synth
     torch.cuda.set_device(0)
+    if args.copy_calib:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log("generating the W-projection workload")
     t0 = time.perf_counter()
     wl = synth.config2_wproj(dft_device="cuda")
@@ -199,14 +358,7 @@ def main():
             res[f]["speedup_vs_f64"] = res[f]["vis_per_s"] / res["f64"]["vis_per_s"]
     del grids
     head = res[args.form]
-    npol = wl.grid.npol
-    flops = 8.0 * npol * head["taps"]
-    t_k = head["grid_kernel_ms"] * 1e-3
-    roof = {"bound": "alu", "kernel": "k_grid (gridder)", "achieved": flops / t_k / 1e12,
-            "peak": PEAK[args.form] / 1e12, "unit": "TFLOP/s",
-            "frac": (flops / t_k) / PEAK[args.form], "traffic": None,
-            "algorithmic_flops_per_launch": flops,
-            "unit_of_work": "8 flops x 4 pols per kernel tap of each sample group"}
+    roof = gridder_roofline(wl, args.form, head)
     out = {
         "metric": "visibilities gridded+degridded/sec",
         "value": head["vis_per_s"],
@@ -228,8 +380,17 @@ def main():
         "roofline": roof,
         "forms": res,
     }
+    if args.serving_jobs > 0:
+        log("serving stream of %d jobs" % args.serving_jobs)
+        del wl
+        torch.cuda.empty_cache()
+        out["serving"] = serving_bench(args.serving_jobs, form=args.form)
+        log("  ", json.dumps(out["serving"]))
+        wl = None
     if not args.no_cpu_baseline:
         log("cpu baseline")
+        if wl is None:
+            wl = synth.config2_wproj(dft_device="cuda")
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 

@@ -281,6 +281,36 @@ __global__ void k_chunk_end(int32_t *chunk_start, int64_t n_chunks, int64_t n) {
     if (threadIdx.x == 0) chunk_start[n_chunks] = (int32_t)n;
 }
 
+// Group of every pair in natural (row, channel) order: >= 0 kept, -1
+// dropped, -2 skipped channel.
+__global__ void k_pair_group(const int32_t *order, const int32_t *gidx, int64_t n_kept,
+                             int64_t n_pairs, int32_t *pair_group) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_pairs) return;
+    int32_t v = order[i];
+    int32_t pair = v & ~(1 << 30);
+    pair_group[pair] = i < n_kept ? gidx[i] : (((v >> 30) & 1) ? -2 : -1);
+}
+
+// Row period: the smallest r for which rows i and i + r have nearly the same
+// (u, v, w) for all of the first 64 rows (the next sample of the same
+// baseline in time-major data).  Only the work order of the presum and
+// expand kernels depends on it, never a result.
+__global__ void k_row_period(const double *uvw, int64_t nrow, int32_t rmax, int32_t *best) {
+    int32_t r = blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (r > rmax) return;
+    int64_t nchk = nrow - r < 64 ? nrow - r : 64;
+    if (nchk < 4) return;
+    for (int64_t i = 0; i < nchk; ++i) {
+        double a0 = uvw[3 * i], a1 = uvw[3 * i + 1], a2 = uvw[3 * i + 2];
+        double b0 = uvw[3 * (i + r)], b1 = uvw[3 * (i + r) + 1], b2 = uvw[3 * (i + r) + 2];
+        double d = fabs(a0 - b0) + fabs(a1 - b1) + fabs(a2 - b2);
+        double s = fabs(a0) + fabs(a1) + fabs(a2);
+        if (!(d <= 1e-2 * s + 1e-3)) return;
+    }
+    atomicMin(best, r);
+}
+
 __global__ void k_taps(const GroupMeta *groups, int64_t n_groups, const int32_t *h,
                        unsigned long long *out) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -325,6 +355,7 @@ PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max) {
     L.chan = take(sizeof(ChanConst) * (nchan > 0 ? nchan : 1));
     L.order = take(sizeof(int32_t) * n);
     L.gidx = take(sizeof(int32_t) * n);
+    L.pair_group = take(sizeof(int32_t) * n);
     L.group_start = take(sizeof(int32_t) * (n + 1));
     L.groups = take(sizeof(GroupMeta) * n);
     L.tp_group = take(sizeof(int32_t) * ntp);
@@ -364,6 +395,8 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     size_t temp_bytes = sort_temp_bytes(n, L.max_tp);
     P->order = order;
     P->gidx = gidx;
+    P->pair_group = (int32_t *)(buf + L.pair_group);
+    P->period = 0;
     P->group_start = (int32_t *)(buf + L.group_start);
     P->groups = (GroupMeta *)(buf + L.groups);
     P->tp_group = (int32_t *)(buf + L.tp_group);
@@ -451,6 +484,23 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->n_tile_pairs = ntp;
     P->n_chunks = nch;
     P->taps = (int64_t)taps;
+
+    // natural-order group map and the row period of the data
+    hipLaunchKernelGGL(k_pair_group, dim3(blocks(n, 256)), dim3(256), 0, s, order, gidx,
+                       (int64_t)nk, n, P->pair_group);
+    int32_t rmax = (int32_t)std::min<int64_t>(P->nrow - 1, 1 << 16);
+    P->period = 0;
+    if (rmax >= 1) {
+        int32_t *best = (int32_t *)counter;
+        int32_t big = 0x7fffffff;
+        if ((e = upload_words(&big, sizeof big, best, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_row_period, dim3(blocks(rmax, 256)), dim3(256), 0, s, uvw,
+                           P->nrow, rmax, best);
+        int32_t r = big;
+        (void)hipMemcpyAsync(&r, best, 4, hipMemcpyDeviceToHost, s);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        if (r != big) P->period = (int64_t)r * P->nchan;
+    }
     return hipGetLastError();
 }
 

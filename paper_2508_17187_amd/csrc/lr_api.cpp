@@ -266,7 +266,7 @@ int32_t chunk_pairs() {
     static int32_t v = [] {
         const char *e = getenv("LR_TILE_CHUNK");
         int x = e ? atoi(e) : 0;
-        return x >= 1 && x <= (1 << 20) ? x : 64;
+        return x >= 1 && x <= kChunkMax ? x : kChunkMax;
     }();
     return v;
 }

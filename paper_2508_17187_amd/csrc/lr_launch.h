@@ -15,7 +15,7 @@ struct KeyLayout {
 };
 
 struct PlanLayout {
-    size_t chan, order, gidx, group_start, groups, tp_group, chunk_start, chunk_tile,
+    size_t chan, order, gidx, pair_group, group_start, groups, tp_group, chunk_start, chunk_tile,
         chunk_excl, persistent;
     size_t keys_a, keys_b, vals_a, flags, scan, counter, temp;
     int64_t max_tp;

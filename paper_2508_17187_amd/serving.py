@@ -42,6 +42,7 @@ class Job:
     slot: Optional[int] = None
     error: Optional[str] = None
     result: Any = None
+    cf_cold: bool = False        # this job brought its CF into residency
 
 
 class Scheduler:
@@ -209,6 +210,10 @@ class Server:
         with self.lock:
             jobs = list(self.sched.done) + list(self.sched.rejected)
             s = latency_stats(jobs)
+            cold = [j for j in jobs if j.cf_cold]
+            warm = [j for j in jobs if not j.cf_cold]
+            s["cold"] = {k: latency_stats(cold)[k] for k in ("jobs_done", "p50_s", "p99_s")}
+            s["warm"] = {k: latency_stats(warm)[k] for k in ("jobs_done", "p50_s", "p99_s")}
             s["peak_hbm_bytes"] = self.sched.peak_used
             s["hbm_budget"] = self.sched.budget
             s["resident_cfs"] = len(self.sched.cf)
@@ -219,6 +224,7 @@ class Server:
         with self.lock:
             while not self.stop:
                 for job, new_cf in self.sched.admit(self.clock()):
+                    job.cf_cold = new_cf
                     if new_cf:
                         self.cf_ready[job.cf_key] = threading.Event()
                     self.slot_q[job.slot].append((job, new_cf))
