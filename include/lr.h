@@ -113,7 +113,8 @@ typedef struct {
 typedef struct lr_cf lr_cf;       /* host handle over a caller-owned device blob */
 typedef struct lr_plan lr_plan;   /* host handle over a caller-owned device blob */
 
-/* Visibility data.  Device pointers unless noted. */
+/* Visibility data.  Device pointers unless noted; uvw, vis and weight must be
+ * 16-byte aligned (LR_E_ARG otherwise). */
 typedef struct {
     int64_t nrow;
     int32_t nchan, npol, nant;

@@ -31,6 +31,29 @@ struct cpx {
     T x, y;
 };
 
+// Per-sample records (npol values) moved in 16-byte pieces when their size
+// allows: callers pass pointers to whole records, which are 16-byte aligned
+// whenever the record size is a multiple of 16.
+template <typename E, int N>
+__device__ __forceinline__ void vload(const E *p, E (&out)[N]) {
+    if constexpr ((N * sizeof(E)) % 16 == 0) {
+        const E *q = (const E *)__builtin_assume_aligned(p, 16);
+        __builtin_memcpy(out, q, N * sizeof(E));
+    } else {
+        for (int i = 0; i < N; ++i) out[i] = p[i];
+    }
+}
+
+template <typename E, int N>
+__device__ __forceinline__ void vstore(E *p, const E (&in)[N]) {
+    if constexpr ((N * sizeof(E)) % 16 == 0) {
+        E *q = (E *)__builtin_assume_aligned(p, 16);
+        __builtin_memcpy(q, in, N * sizeof(E));
+    } else {
+        for (int i = 0; i < N; ++i) p[i] = in[i];
+    }
+}
+
 __global__ void k_zero(uint4 *p, int64_t n16, uint8_t *tail, int ntail) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n16) p[i] = make_uint4(0, 0, 0, 0);
@@ -248,49 +271,55 @@ __global__ __launch_bounds__(256) void k_presum(
 }
 
 // ---------------------------------------------------------------------------
-// The same presum walking the pairs in natural order along tracks: when the
-// data repeat with a period of L pairs (time-major rows), pair c + m L is the
-// next sample of the track of pair c.  A lane owns column c for TM steps and
-// accumulates while its group is unchanged, flushing with atomics on a
-// change; the 64 lanes of a wavefront read 64 consecutive pairs at each step.
+// The same presum in natural order along tracks: when the data repeat with
+// a period of L pairs (time-major rows), pair c + m L is the next sample of
+// the track of pair c.  A wavefront covers 8 consecutive columns c x 8
+// consecutive steps m (lane = 8 * step + column), so every lane issues its
+// loads at once and 8 consecutive pairs are contiguous; a 3-step segmented
+// shuffle reduces along the steps and the last lane of each run of equal
+// groups adds it to A with one atomic.
+constexpr int kColW = 8, kColT = 8, kColBlocks = 8;
+
 template <typename T, int NPOL, bool UNIT, bool SUMS>
 __global__ __launch_bounds__(256) void k_presum_col(
-    int64_t n_pairs, int64_t L, int32_t TM, const int32_t *pair_group,
+    int64_t n_pairs, int64_t L, int64_t ncb, const int32_t *pair_group,
     const GroupMeta *groups, const T *vis, const T *weight, cpx<T> *A, double *sumwt,
     long long *counters) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int64_t ncolw = (L + 63) / 64;
-    const int64_t c = (wave % ncolw) * 64 + lane;
-    const int64_t m0 = (wave / ncolw) * TM;
+    const int cl = lane & (kColW - 1), tl = lane / kColW;
+    const int64_t c = (wave % ncb) * kColW + cl;
+    const int64_t mw = (wave / ncb) * (kColT * kColBlocks);
     long long kept = 0, flagged = 0, dropped = 0;
     double sw[NPOL];
-    cpx<T> acc[NPOL];
+    cpx<T> carry[NPOL];
     for (int p = 0; p < NPOL; ++p) {
         sw[p] = 0.0;
-        acc[p] = {(T)0, (T)0};
+        carry[p] = {(T)0, (T)0};
     }
-    int cur = -1, plane = -1;
-    auto flush = [&]() {
-        if (SUMS && cur >= 0)
-            for (int p = 0; p < NPOL; ++p) {
-                atomicAdd(&A[(int64_t)cur * NPOL + p].x, acc[p].x);
-                if (!UNIT) atomicAdd(&A[(int64_t)cur * NPOL + p].y, acc[p].y);
-            }
-        for (int p = 0; p < NPOL; ++p) acc[p] = {(T)0, (T)0};
+    int carry_g = -1, plane = -1;
+    auto add_to_A = [&](int g, const cpx<T> *v) {
+        for (int p = 0; p < NPOL; ++p) {
+            atomicAdd(&A[(int64_t)g * NPOL + p].x, v[p].x);
+            if (!UNIT) atomicAdd(&A[(int64_t)g * NPOL + p].y, v[p].y);
+        }
     };
-    if (c < L) {
-        for (int64_t m = m0; m < m0 + TM; ++m) {
-            const int64_t j = c + m * L;
-            if (j >= n_pairs) break;
-            const int g = pair_group[j];
-            if (g != cur) {
-                flush();
-                cur = g;
-                if (g >= 0) plane = groups[g].plane;
-            }
+    for (int b = 0; b < kColBlocks; ++b) {
+        const int64_t m = mw + b * kColT + tl;
+        const int64_t j = c + m * L;
+        const bool valid = c < L && j < n_pairs;
+        cpx<T> a[NPOL];
+        for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
+        const int g = valid ? pair_group[j] : -1;
+        if (valid) {
+            if (g >= 0) plane = groups[g].plane;
+            T wv[NPOL];
+            cpx<T> vv[NPOL];
+            if (weight) vload(weight + j * NPOL, wv);
+            else for (int p = 0; p < NPOL; ++p) wv[p] = (T)1;
+            if (SUMS && !UNIT && g >= 0) vload((const cpx<T> *)vis + j * NPOL, vv);
             for (int p = 0; p < NPOL; ++p) {
-                T W = weight ? weight[j * NPOL + p] : (T)1;
+                const T W = wv[p];
                 if (g < 0) {
                     if (g == -2 || W == (T)0) ++flagged; else ++dropped;
                 } else if (W != (T)0) {
@@ -298,11 +327,10 @@ __global__ __launch_bounds__(256) void k_presum_col(
                     sw[p] += (double)W;
                     if (SUMS) {
                         if (UNIT) {
-                            acc[p].x += W;
+                            a[p].x = W;
                         } else {
-                            const T *v = vis + 2 * (j * NPOL + p);
-                            acc[p].x = fma(W, v[0], acc[p].x);
-                            acc[p].y = fma(W, v[1], acc[p].y);
+                            a[p].x = W * vv[p].x;
+                            a[p].y = W * vv[p].y;
                         }
                     }
                 } else {
@@ -310,8 +338,42 @@ __global__ __launch_bounds__(256) void k_presum_col(
                 }
             }
         }
-        flush();
+        if (!SUMS) continue;
+        // the first step of a column continues the run carried from the last
+        // step of the previous block, or closes it
+        if (tl == 0 && carry_g >= 0) {
+            if (carry_g == g) {
+                for (int p = 0; p < NPOL; ++p) {
+                    a[p].x += carry[p].x;
+                    a[p].y += carry[p].y;
+                }
+            } else {
+                add_to_A(carry_g, carry);
+            }
+        }
+        const int key = g >= 0 ? g : -1 - lane;     // lanes without a group never merge
+        for (int off = kColW; off < 64; off <<= 1) {
+            const int ko = __shfl_up(key, off);
+            const bool take = lane >= off && ko == key;
+            for (int p = 0; p < NPOL; ++p) {
+                const T x = __shfl_up(a[p].x, off), y = __shfl_up(a[p].y, off);
+                if (take) {
+                    a[p].x += x;
+                    a[p].y += y;
+                }
+            }
+        }
+        const int kn = __shfl_down(key, kColW);
+        if (g >= 0 && tl != kColT - 1 && kn != key) add_to_A(g, a);   // run ended in the block
+        // hand the last step's run to the first step of the next block
+        const int src = (lane & (kColW - 1)) + (kColT - 1) * kColW;
+        carry_g = __shfl(g, src);
+        for (int p = 0; p < NPOL; ++p) {
+            carry[p].x = __shfl(a[p].x, src);
+            carry[p].y = __shfl(a[p].y, src);
+        }
     }
+    if (SUMS && tl == 0 && carry_g >= 0) add_to_A(carry_g, carry);
     if (counters) {
         kept = wave_sum_ll(kept);
         flagged = wave_sum_ll(flagged);
@@ -338,40 +400,13 @@ __global__ __launch_bounds__(256) void k_presum_col(
     }
 }
 
-// Expand along tracks, same traversal: every pair gets its group's value
-// (0 when dropped, skipped or flagged); 64 consecutive pairs per store.
-template <typename T, int NPOL>
-__global__ __launch_bounds__(256) void k_expand_col(int64_t n_pairs, int64_t L, int32_t TM,
-                                                    const int32_t *pair_group,
-                                                    const cpx<T> *Vg, cpx<T> *vis,
-                                                    const T *weight) {
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    const int64_t ncolw = (L + 63) / 64;
-    const int64_t c = (wave % ncolw) * 64 + lane;
-    const int64_t m0 = (wave / ncolw) * TM;
-    if (c >= L) return;
-    for (int64_t m = m0; m < m0 + TM; ++m) {
-        const int64_t j = c + m * L;
-        if (j >= n_pairs) break;
-        const int g = pair_group[j];
-        for (int p = 0; p < NPOL; ++p) {
-            bool zero = g < 0 || (weight && weight[j * NPOL + p] == (T)0);
-            vis[j * NPOL + p] = zero ? cpx<T>{(T)0, (T)0} : Vg[(int64_t)g * NPOL + p];
-        }
-    }
-}
-
-// Work shape of the track kernels: TM steps per lane, enough wavefronts to
-// fill the chip.
-static void col_shape(int64_t n_pairs, int64_t L, int32_t &TM, int64_t &blocks) {
+// Work shape of the track presum: ncb column blocks x ceil(M / 64) step
+// blocks, one wavefront each.
+static void col_shape(int64_t n_pairs, int64_t L, int64_t &ncb, int64_t &blocks) {
     int64_t M = (n_pairs + L - 1) / L;
-    int64_t ncolw = (L + 63) / 64;
-    int64_t tm = (M * ncolw + 4095) / 4096;
-    if (tm < 1) tm = 1;
-    if (tm > M) tm = M;
-    TM = (int32_t)tm;
-    int64_t waves = ncolw * ((M + tm - 1) / tm);
+    ncb = (L + kColW - 1) / kColW;
+    const int64_t span = kColT * kColBlocks;
+    int64_t waves = ncb * ((M + span - 1) / span);
     blocks = (waves + 3) / 4;
 }
 
@@ -422,8 +457,11 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     const int rest = key / a.ntx;
     const int ty = rest % a.nty;
     const int P = rest / a.nty;
+    // thread t owns column t % 32 of rows 4 (t / 32) .. 4 (t / 32) + 3, so a
+    // wavefront owns a band of 8 rows and skips footprints that miss it
     const int x = tx * kTile + (threadIdx.x & 31);
-    const int yb = ty * kTile + (threadIdx.x >> 5);
+    const int yb = ty * kTile + 4 * (threadIdx.x >> 5);
+    const int band0 = ty * kTile + 8 * (threadIdx.x >> 6);
     const cpx<T> *Av = (const cpx<T> *)a.A;
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const int32_t g = a.tp_group[s0 + t];
@@ -446,9 +484,9 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     for (int j = 0; j < 4; ++j)
         for (int p = 0; p < NPOL; ++p) acc[j][p] = {(T)0, (T)0};
     int touched = 0;
-#pragma unroll 2
     for (int t = 0; t < n; ++t) {
         const TileItem ti = items[t];
+        if (ti.by >= band0 + 8 || ti.by + ti.S <= band0) continue;   // wave-uniform
         const int dx = x - ti.bx;
         const bool inx = (unsigned)dx < (unsigned)ti.S;
         cpx<T> cv[4];
@@ -456,7 +494,7 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
         int inm = 0;
         // the four cell loads are issued together, predicated instead of branched
         for (int j = 0; j < 4; ++j) {
-            const int dy = yb + 8 * j - ti.by;
+            const int dy = yb + j - ti.by;
             dys[j] = dy;
             const bool in = inx && (unsigned)dy < (unsigned)ti.S;
             inm |= in ? (1 << j) : 0;
@@ -477,7 +515,7 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     T *grid = (T *)a.grid;
     for (int j = 0; j < 4; ++j) {
         if (!(touched & (1 << j))) continue;
-        const int y = yb + 8 * j;
+        const int y = yb + j;
         for (int p = 0; p < NPOL; ++p) {
             const int64_t base = ((int64_t)P * NPOL + p) * a.pol_stride;
             T *q = grid + 2 * (base + (int64_t)y * a.nx + x);
@@ -493,129 +531,6 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
             } else {
                 atomicAdd(q, acc[j][p].x);
                 atomicAdd(q + 1, acc[j][p].y);
-            }
-        }
-    }
-}
-
-// Packed variant for sparse tiles: the cells that each pair's footprint
-// covers inside the tile are numbered consecutively across the chunk, thread
-// t takes items t, t + 256, ..., and every item adds its npol products into an
-// LDS copy of the tile with LDS atomics.  No thread idles on cells outside a
-// footprint; the tile is then written once as in the register variant.
-struct PackItem {
-    int64_t cf_off;
-    int32_t tap0;     // sub-kernel index of the first covered cell
-    int32_t S, w;     // support, width of the covered rectangle
-    int32_t cell0;    // tile-local index of the first covered cell
-    int32_t dx0, dy0; // offsets of that cell from the footprint origin
-    int32_t h, conj;
-    float sc;
-};
-
-template <typename T, int ST, int NPOL, bool PO, bool PSF>
-__global__ __launch_bounds__(256) void k_grid_tile_packed(TileArgs a) {
-    __shared__ T accr[NPOL][kTile * kTile];
-    __shared__ T acci[NPOL][kTile * kTile];
-    __shared__ PackItem items[kChunkMax];
-    __shared__ int32_t pre[kChunkMax + 1];
-    __shared__ cpx<T> avs[kChunkMax * NPOL];
-    __shared__ GroupMeta gms[PO ? kChunkMax : 1];
-    const int c = blockIdx.x;
-    const int32_t s0 = a.chunk_start[c];
-    const int n = a.chunk_start[c + 1] - s0;
-    const int32_t key = a.chunk_tile[c];
-    const bool excl = !PSF && a.chunk_excl[c];
-    const int tx = key % a.ntx;
-    const int rest = key / a.ntx;
-    const int ty = rest % a.nty;
-    const int P = rest / a.nty;
-    const int X0 = tx * kTile, Y0 = ty * kTile;
-    const cpx<T> *Av = (const cpx<T> *)a.A;
-    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x)
-        for (int p = 0; p < NPOL; ++p) {
-            accr[p][i] = (T)0;
-            acci[p][i] = (T)0;
-        }
-    int32_t cnt = 0;
-    if (threadIdx.x < n) {
-        const int t = threadIdx.x;
-        const int32_t g = a.tp_group[s0 + t];
-        const GroupMeta gm = a.groups[g];
-        const int h = a.cf.h[gm.k];
-        const int S = 2 * h + 1;
-        const int bx = gm.pu - h, by = gm.pv - h;
-        const int x0 = max(bx, X0), x1 = min(bx + S, X0 + kTile);
-        const int y0 = max(by, Y0), y1 = min(by + S, Y0 + kTile);
-        PackItem it;
-        it.cf_off = gm.cf_off;
-        it.S = S;
-        it.w = x1 - x0;
-        it.dx0 = x0 - bx;
-        it.dy0 = y0 - by;
-        it.tap0 = it.dy0 * S + it.dx0;
-        it.cell0 = (y0 - Y0) * kTile + (x0 - X0);
-        it.h = h;
-        it.conj = gm.conj;
-        it.sc = a.cf.scale[gm.fg * a.cf.n_w + gm.k];
-        items[t] = it;
-        cnt = (x1 - x0) * (y1 - y0);
-        for (int p = 0; p < NPOL; ++p) avs[t * NPOL + p] = Av[(int64_t)g * NPOL + p];
-        if (PO) gms[t] = gm;
-    }
-    // prefix of the covered-cell counts (n <= 64: one wavefront scan)
-    if (threadIdx.x < 64) {
-        int32_t v = cnt;
-        for (int off = 1; off < 64; off <<= 1) {
-            int32_t u = __shfl_up(v, off);
-            if ((int)threadIdx.x >= off) v += u;
-        }
-        pre[threadIdx.x + 1] = v;
-        if (threadIdx.x == 0) pre[0] = 0;
-    }
-    __syncthreads();
-    const int32_t total = pre[n];
-    int cur = 0;
-    for (int32_t i = threadIdx.x; i < total; i += blockDim.x) {
-        while (i >= pre[cur + 1]) ++cur;
-        const PackItem it = items[cur];
-        const int local = i - pre[cur];
-        int cy, cx;
-        divmod_small(local, it.w, 1.0f / (float)it.w, cy, cx);
-        cpx<T> cv = CFElem<ST>::load(a.cf.table, it.cf_off + it.tap0 + cy * it.S + cx, it.sc);
-        if (it.conj) cv.y = -cv.y;
-        if (PO) cv = cmul(cv, phasor<T>(gms[cur], it.dx0 + cx - it.h, it.dy0 + cy - it.h, a.cf.O));
-        const int cell = it.cell0 + cy * kTile + cx;
-        for (int p = 0; p < NPOL; ++p) {
-            const cpx<T> av = avs[cur * NPOL + p];
-            cpx<T> r = {(T)0, (T)0};
-            cmac(r, cv, av);
-            atomicAdd(&accr[p][cell], r.x);
-            atomicAdd(&acci[p][cell], r.y);
-        }
-    }
-    __syncthreads();
-    T *grid = (T *)a.grid;
-    for (int i = threadIdx.x; i < kTile * kTile; i += blockDim.x) {
-        const int x = X0 + (i & (kTile - 1)), y = Y0 + i / kTile;
-        if (x >= a.nx || y >= a.ny) continue;
-        for (int p = 0; p < NPOL; ++p) {
-            const T vr = accr[p][i], vi = acci[p][i];
-            if (vr == (T)0 && vi == (T)0) continue;
-            const int64_t base = ((int64_t)P * NPOL + p) * a.pol_stride;
-            T *q = grid + 2 * (base + (int64_t)y * a.nx + x);
-            if (PSF) {
-                T *m = grid + 2 * (base + (int64_t)(a.ny - y) * a.nx + (a.nx - x));
-                atomicAdd(q, (T)0.5 * vr);
-                atomicAdd(q + 1, (T)0.5 * vi);
-                atomicAdd(m, (T)0.5 * vr);
-                atomicAdd(m + 1, -(T)0.5 * vi);
-            } else if (excl) {
-                q[0] += vr;
-                q[1] += vi;
-            } else {
-                atomicAdd(q, vr);
-                atomicAdd(q + 1, vi);
             }
         }
     }
@@ -680,23 +595,22 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
     }
 }
 
+// Expand: one thread per pair in natural order; the group's value comes from
+// the small per-group array (0 for dropped, skipped and flagged samples).
 template <typename T, int NPOL>
-__global__ __launch_bounds__(256) void k_expand(int64_t n_kept, int64_t n_pairs,
-                                                const int32_t *order, const int32_t *gidx,
+__global__ __launch_bounds__(256) void k_expand(int64_t n_pairs, const int32_t *pair_group,
                                                 const cpx<T> *Vg, cpx<T> *vis,
                                                 const T *weight) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_pairs) return;
-    int64_t pair = order[i] & ~(1 << 30);
-    if (i < n_kept) {
-        int64_t g = gidx[i];
-        for (int p = 0; p < NPOL; ++p) {
-            bool flag = weight && weight[pair * NPOL + p] == (T)0;
-            vis[pair * NPOL + p] = flag ? cpx<T>{(T)0, (T)0} : Vg[g * NPOL + p];
-        }
-    } else {
-        for (int p = 0; p < NPOL; ++p) vis[pair * NPOL + p] = {(T)0, (T)0};
-    }
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n_pairs) return;
+    const int g = pair_group[j];
+    cpx<T> out[NPOL];
+    T w[NPOL];
+    if (weight) vload(weight + j * NPOL, w);
+    if (g >= 0) vload(Vg + (int64_t)g * NPOL, out);
+    for (int p = 0; p < NPOL; ++p)
+        if (g < 0 || (weight && w[p] == (T)0)) out[p] = {(T)0, (T)0};
+    vstore(vis + j * NPOL, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -715,21 +629,20 @@ static hipError_t presum_t(const lr_plan *P, const VisArgs &v, void *A, double *
         if (e != hipSuccess) return e;
     }
     if (P->period > 0) {
-        int32_t TM;
-        int64_t nb;
-        col_shape(P->n_pairs, P->period, TM, nb);
+        int64_t ncb, nb;
+        col_shape(P->n_pairs, P->period, ncb, nb);
         dim3 g2((unsigned)nb);
         if (!sums)
             hipLaunchKernelGGL((k_presum_col<T, NPOL, false, false>), g2, blk, 0, s,
-                               P->n_pairs, P->period, TM, P->pair_group, P->groups, vis, wt,
+                               P->n_pairs, P->period, ncb, P->pair_group, P->groups, vis, wt,
                                (cpx<T> *)A, sumwt, cnt);
         else if (v.unit_vis)
             hipLaunchKernelGGL((k_presum_col<T, NPOL, true, true>), g2, blk, 0, s, P->n_pairs,
-                               P->period, TM, P->pair_group, P->groups, vis, wt, (cpx<T> *)A,
+                               P->period, ncb, P->pair_group, P->groups, vis, wt, (cpx<T> *)A,
                                sumwt, cnt);
         else
             hipLaunchKernelGGL((k_presum_col<T, NPOL, false, true>), g2, blk, 0, s,
-                               P->n_pairs, P->period, TM, P->pair_group, P->groups, vis, wt,
+                               P->n_pairs, P->period, ncb, P->pair_group, P->groups, vis, wt,
                                (cpx<T> *)A, sumwt, cnt);
         return hipGetLastError();
     }
@@ -773,53 +686,28 @@ hipError_t launch_counts(const lr_plan *P, const void *weight, int precision, in
     return presum_np<float>(P, v, nullptr, sumwt, counters, false, s);
 }
 
-template <typename T, int ST, int NPOL, bool PACKED>
-static hipError_t grid_t2(const TileArgs &ta, int64_t n_chunks, bool po, bool psf,
-                          hipStream_t s) {
-    dim3 grd((unsigned)n_chunks), blk(256);
-#define LR_GRID_LAUNCH(PO_, PSF_)                                                            \
-    do {                                                                                     \
-        if (PACKED)                                                                          \
-            hipLaunchKernelGGL((k_grid_tile_packed<T, ST, NPOL, PO_, PSF_>), grd, blk, 0, s, \
-                               ta);                                                          \
-        else                                                                                 \
-            hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, PO_, PSF_>), grd, blk, 0, s, ta);   \
-    } while (0)
-    if (po) {
-        if (psf) LR_GRID_LAUNCH(true, true); else LR_GRID_LAUNCH(true, false);
-    } else {
-        if (psf) LR_GRID_LAUNCH(false, true); else LR_GRID_LAUNCH(false, false);
-    }
-#undef LR_GRID_LAUNCH
-    return hipGetLastError();
-}
-
 template <typename T, int ST, int NPOL>
-static hipError_t grid_t(const TileArgs &ta, int64_t n_chunks, bool po, bool psf, bool packed,
+static hipError_t grid_t(const TileArgs &ta, int64_t n_chunks, bool po, bool psf,
                          hipStream_t s) {
-    return packed ? grid_t2<T, ST, NPOL, true>(ta, n_chunks, po, psf, s)
-                  : grid_t2<T, ST, NPOL, false>(ta, n_chunks, po, psf, s);
+    dim3 grd((unsigned)n_chunks), blk(256);
+    if (po) {
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, true>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, false>), grd, blk, 0, s, ta);
+    } else {
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, true>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false>), grd, blk, 0, s, ta);
+    }
+    return hipGetLastError();
 }
 
 template <typename T, int ST>
 static hipError_t grid_np(const TileArgs &ta, int64_t n_chunks, int npol, bool po, bool psf,
-                          bool packed, hipStream_t s) {
+                          hipStream_t s) {
     switch (npol) {
-        case 1: return grid_t<T, ST, 1>(ta, n_chunks, po, psf, packed, s);
-        case 2: return grid_t<T, ST, 2>(ta, n_chunks, po, psf, packed, s);
-        default: return grid_t<T, ST, 4>(ta, n_chunks, po, psf, packed, s);
+        case 1: return grid_t<T, ST, 1>(ta, n_chunks, po, psf, s);
+        case 2: return grid_t<T, ST, 2>(ta, n_chunks, po, psf, s);
+        default: return grid_t<T, ST, 4>(ta, n_chunks, po, psf, s);
     }
-}
-
-// Which tile gridder: the packed one when footprints cover a small share of
-// the tiles they touch, else the register one.  LR_GRIDDER=packed|register
-// forces a variant (both give the same sums up to rounding order).
-static bool use_packed(const lr_plan *P) {
-    const char *e = getenv("LR_GRIDDER");
-    if (e && e[0] == 'p') return true;
-    if (e && e[0] == 'r') return false;
-    double cover = (double)P->taps / ((double)P->n_tile_pairs * kTile * kTile);
-    return cover < 0.5;
 }
 
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
@@ -830,13 +718,12 @@ hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *
                 cf, nx, ny, (nx + kTile - 1) / kTile, (ny + kTile - 1) / kTile,
                 (int64_t)nx * ny};
     bool po = P->po != 0;
-    bool pk = use_packed(P);
     int64_t nc = P->n_chunks;
     switch (precision) {
-        case LR_F64: return grid_np<double, LR_F64>(ta, nc, npol, po, psf, pk, s);
-        case LR_F32: return grid_np<float, LR_F32>(ta, nc, npol, po, psf, pk, s);
-        case LR_F32_CF16: return grid_np<float, LR_F32_CF16>(ta, nc, npol, po, psf, pk, s);
-        default: return grid_np<float, LR_F32_CFBF16>(ta, nc, npol, po, psf, pk, s);
+        case LR_F64: return grid_np<double, LR_F64>(ta, nc, npol, po, psf, s);
+        case LR_F32: return grid_np<float, LR_F32>(ta, nc, npol, po, psf, s);
+        case LR_F32_CF16: return grid_np<float, LR_F32_CF16>(ta, nc, npol, po, psf, s);
+        default: return grid_np<float, LR_F32_CFBF16>(ta, nc, npol, po, psf, s);
     }
 }
 
@@ -877,40 +764,18 @@ static hipError_t expand_t(const lr_plan *P, const void *Vg, void *vis, const vo
     const cpx<T> *V = (const cpx<T> *)Vg;
     cpx<T> *out = (cpx<T> *)vis;
     const T *w = (const T *)weight;
-    if (P->period > 0) {
-        int32_t TM;
-        int64_t nb;
-        col_shape(P->n_pairs, P->period, TM, nb);
-        dim3 g2((unsigned)nb);
-        const int32_t *pg = P->pair_group;
-        int64_t L = P->period;
-        switch (npol) {
-            case 1:
-                hipLaunchKernelGGL((k_expand_col<T, 1>), g2, blk, 0, s, P->n_pairs, L, TM, pg,
-                                   V, out, w);
-                break;
-            case 2:
-                hipLaunchKernelGGL((k_expand_col<T, 2>), g2, blk, 0, s, P->n_pairs, L, TM, pg,
-                                   V, out, w);
-                break;
-            default:
-                hipLaunchKernelGGL((k_expand_col<T, 4>), g2, blk, 0, s, P->n_pairs, L, TM, pg,
-                                   V, out, w);
-        }
-        return hipGetLastError();
-    }
     switch (npol) {
         case 1:
-            hipLaunchKernelGGL((k_expand<T, 1>), grd, blk, 0, s, P->n_kept, P->n_pairs,
-                               P->order, P->gidx, V, out, w);
+            hipLaunchKernelGGL((k_expand<T, 1>), grd, blk, 0, s, P->n_pairs, P->pair_group, V,
+                               out, w);
             break;
         case 2:
-            hipLaunchKernelGGL((k_expand<T, 2>), grd, blk, 0, s, P->n_kept, P->n_pairs,
-                               P->order, P->gidx, V, out, w);
+            hipLaunchKernelGGL((k_expand<T, 2>), grd, blk, 0, s, P->n_pairs, P->pair_group, V,
+                               out, w);
             break;
         default:
-            hipLaunchKernelGGL((k_expand<T, 4>), grd, blk, 0, s, P->n_kept, P->n_pairs,
-                               P->order, P->gidx, V, out, w);
+            hipLaunchKernelGGL((k_expand<T, 4>), grd, blk, 0, s, P->n_pairs, P->pair_group, V,
+                               out, w);
     }
     return hipGetLastError();
 }

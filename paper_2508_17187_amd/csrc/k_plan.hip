@@ -418,7 +418,11 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
         return e;
     if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
     P->n_kept = (int64_t)nk;
-    if (nk == 0) return hipSuccess;
+    if (nk == 0) {
+        hipLaunchKernelGGL(k_pair_group, dim3(blocks(n, 256)), dim3(256), 0, s, order, gidx,
+                           (int64_t)0, n, P->pair_group);
+        return hipGetLastError();
+    }
 
     hipLaunchKernelGGL(k_group_flags, dim3(blocks(nk, 256)), dim3(256), 0, s, keys_b,
                        (int64_t)nk, P->merged, flags);

@@ -209,6 +209,8 @@ lr_status check_vis(const lr_cf *cf, const lr_vis *v, bool need_vis, bool need_w
         if (fg < 0 || fg >= cf->spec.n_fg) return fail(LR_E_ARG, "chan_fg[%d] out of range", c);
     }
     if (need_vis && v->nrow > 0 && !v->vis) return fail(LR_E_ARG, "vis is NULL");
+    if (((uintptr_t)v->vis | (uintptr_t)v->weight | (uintptr_t)v->uvw) & 15)
+        return fail(LR_E_ARG, "uvw, vis and weight must be 16-byte aligned");
     if (need_weight && v->nrow > 0 && !v->weight) return fail(LR_E_ARG, "weight is NULL");
     bool po = v->ant1 || v->ant2 || v->ant_dlm;
     if (po && !(v->ant1 && v->ant2 && v->ant_dlm && v->nant > 0))

@@ -184,26 +184,6 @@ def test_grid_parity(awp, form):
     assert c_ref[0] > 0 and c_ref[1] > 0 and c_ref[2] > 0
 
 
-@pytest.mark.parametrize("variant", ["register", "packed"])
-@pytest.mark.parametrize("form", ["f64", "f32"])
-def test_both_tile_gridders(awp, awp_po, monkeypatch, variant, form):
-    """The register (cell-owning) and packed (LDS) tile gridders, forced in
-    turn, on plain, pointing and PSF gridding."""
-    monkeypatch.setenv("LR_GRIDDER", variant)
-    for wl, ocf in (awp, awp_po):
-        g, _, _ = run_grid(wl, form)
-        pr = Problem.from_workload(wl, ocf)
-        assert rel(g, pr.grid(wl.vis, wl.weight)) <= TOL[form], variant
-    wl, ocf = awp
-    p = PREC[form]
-    cf = W.build_cf(wl, p)
-    v = W.device_vis(wl, p, with_vis=False)
-    gp = W.empty_grid(wl, p)
-    lr.lr_make_psf(cf, v, p, gp)
-    ref = Problem.from_workload(wl, ocf).psf(wl.weight)[0]
-    assert rel(gp.cpu().numpy(), ref) <= TOL[form]
-
-
 def test_rows_in_any_order(awp):
     """Time-major rows let presum / expand walk tracks in natural order; a
     shuffled row order has no period and takes the sorted-gather path.  Both
