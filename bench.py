@@ -1,8 +1,9 @@
 #!/usr/bin/env python3
 """Benchmark of the gridding / degridding hot path on one MI355X.
 
-A step = zero the grid, grid every visibility (presum + gridder), degrid
-every visibility from that grid (degridder + expand), over the W-projection
+A step = grid every visibility into a fresh grid (lr_grid_overwrite: clear
+of the tiles no chunk owns, presum, gridder), then degrid every visibility
+from that grid (degridder + expand), over the W-projection
 workload: 351 baselines, 600 dumps, 16 channels, 4 correlations
 (13,478,400 visibilities), 32 w-planes with supports 17..65, O = 20, onto a
 2048 x 2048 x 4 grid.  Inputs are resident in HBM; the CF table
@@ -80,26 +81,35 @@ def run_form(wl, form, steps, warmup, ev):
     wd = lr._work(lr.LR_OP_DEGRID, cf, vout, p, None)
     info = plan.info()
 
-    def step(prof=None):
-        g.zero_()
+    def step(prof=None, marks=None):
+        if marks:
+            marks[0].record()
         if prof:
             lr.lr_set_profile_events(*prof[0])
-        lr.lr_grid(cf, v, p, g, work=wg)
+        lr.lr_grid_overwrite(cf, v, p, g, work=wg)
+        if marks:
+            marks[1].record()
         if prof:
             lr.lr_set_profile_events(*prof[1])
         lr.lr_degrid(cf, vout, p, g, work=wd)
+        if marks:
+            marks[2].record()
 
     for _ in range(warmup):
         step()
     pairs = [(ev.pair(), ev.pair()) for _ in range(steps)]
+    # whole calls, on the stream the library launches on (torch's current one)
+    marks = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
-        step(pairs[i])
+        step(pairs[i], marks[i])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     kg = [ev.ms(*pr[0]) for pr in pairs]
     kd = [ev.ms(*pr[1]) for pr in pairs]
+    og = [m[0].elapsed_time(m[1]) for m in marks]
+    od = [m[1].elapsed_time(m[2]) for m in marks]
     for pr in pairs:
         ev.free(*pr[0])
         ev.free(*pr[1])
@@ -135,6 +145,8 @@ def run_form(wl, form, steps, warmup, ev):
         "ms_per_step_graph": None if dt_graph is None else 1e3 * dt_graph / steps,
         "grid_kernel_ms": sum(kg) / len(kg),
         "degrid_kernel_ms": sum(kd) / len(kd),
+        "grid_call_ms": sum(og) / len(og),
+        "degrid_call_ms": sum(od) / len(od),
         "cf_build_ms": 1e3 * t_cf,
         "plan_build_ms": 1e3 * t_plan,
         "n_groups": info["n_groups"],
@@ -149,7 +161,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grid_tile_wproj2048_traffic.jso
 KERNEL_SRC = os.path.join(ROOT, "paper_2508_17187_amd", "csrc", "k_grid.hip")
 
 
-def gridder_roofline(wl, form, r):
+def gridder_roofline(wl, form, r, with_traffic=True):
     """Roofline of the gridder kernel (one launch grids all groups).
 
     Algorithmic flops: 8 per complex multiply-add, npol per kernel tap of
@@ -166,6 +178,8 @@ def gridder_roofline(wl, form, r):
     hbm = bytes_ / HBM_PEAK >= flops / PEAK[form]
     traffic = None
     try:
+        if not with_traffic:        # the counter summary covers the W-projection run
+            raise OSError
         tr = json.load(open(TRAFFIC_FILE))
         sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
         if tr.get("kernel_source_sha256") == sha and tr.get("form") == form:
@@ -183,6 +197,25 @@ def gridder_roofline(wl, form, r):
             "traffic": traffic, "algorithmic_bytes_per_launch": bytes_,
             "algorithmic_flops_per_launch": flops, "hbm_frac": bytes_ / t / HBM_PEAK,
             "kernel_ms": r["grid_kernel_ms"]}
+
+
+def gridding_roofline(wl, form, r):
+    """HBM roofline of the whole gridding call (clear of shared tiles,
+    presum, gridder) on a shape where bandwidth binds: algorithmic bytes are
+    the visibilities and weights read once, the per-pair group map, the
+    group sums and kernel taps, and the grid written once."""
+    npol = wl.grid.npol
+    cplx = 16 if form == "f64" else 8
+    real = cplx // 2
+    n_pairs = wl.obs.nrow * wl.obs.nchan
+    grid_bytes = wl.grid.nplane * npol * wl.grid.nx * wl.grid.ny * cplx
+    bytes_ = (n_pairs * npol * (cplx + real) + 4 * n_pairs + r["n_groups"] * npol * cplx
+              + r["taps"] * ELEM[form] + grid_bytes)
+    t = r["grid_call_ms"] * 1e-3
+    return {"bound": "hbm", "scope": "lr_grid_overwrite call (presum + gridder)",
+            "achieved": bytes_ / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": bytes_ / t / HBM_PEAK, "algorithmic_bytes_per_call": bytes_,
+            "call_ms": r["grid_call_ms"]}
 
 
 def serving_bench(n_jobs=256, rate=20.0, budget_gb=64.0, slots=4, form="f32"):
@@ -315,6 +348,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-jobs", type=int, default=256,
                     help="jobs in the serving stream (0 = skip it)")
+    ap.add_argument("--no-ps", dest="ps", action="store_false",
+                    help="skip the Standard-kernel (HBM-bound) workload")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 1 GiB device copy first (scale of the HBM byte counters)")
     args = ap.parse_args()
@@ -357,6 +392,24 @@ def main():
         for f in forms:
             res[f]["speedup_vs_f64"] = res[f]["vis_per_s"] / res["f64"]["vis_per_s"]
     del grids
+    hbm = None
+    if args.ps:
+        # the same data through the Standard kernel (PS, S = 7, O = 100, one
+        # plane): the shape on which HBM bandwidth binds
+        log("standard-kernel (PS) workload")
+        wps = synth.config2_ps(dft_device="cuda")
+        hbm = {"workload": "W-projection data with the Standard kernel: PS only, S=7, "
+                           "O=100, 2048x2048x4 grid", "forms": {}}
+        for f in ("f32", "f64"):
+            r, _, _ = run_form(wps, f, args.steps, args.warmup, ev)
+            hbm["forms"][f] = r
+            log("  ", f, json.dumps(r))
+        hbm["speedup_f32_vs_f64"] = (hbm["forms"]["f32"]["vis_per_s"]
+                                     / hbm["forms"]["f64"]["vis_per_s"])
+        hbm["roofline"] = gridding_roofline(wps, "f32", hbm["forms"]["f32"])
+        hbm["roofline_gridder_kernel"] = gridder_roofline(wps, "f32", hbm["forms"]["f32"],
+                                                          with_traffic=False)
+        del wps
     head = res[args.form]
     roof = gridder_roofline(wl, args.form, head)
     out = {
@@ -380,6 +433,8 @@ def main():
         "roofline": roof,
         "forms": res,
     }
+    if hbm is not None:
+        out["hbm_bound_workload"] = hbm
     if args.serving_jobs > 0:
         log("serving stream of %d jobs" % args.serving_jobs)
         del wl

@@ -216,6 +216,16 @@ lr_status lr_grid(const lr_cf *cf, const lr_vis *vis, lr_precision precision, vo
                   double *sumwt, int64_t *counters, void *work, size_t work_bytes,
                   lr_stream stream);
 
+/* Gridding G as lr_grid, with the outputs replaced instead of accumulated:
+ * grid = G(vis) (every cell of every plane and pol is written, cells no
+ * footprint reaches become 0), sumwt = the sums of weights, counters = the
+ * class counts.  The caller need not clear them first, so a fresh grid
+ * costs one write pass instead of a clear plus a read-modify-write.
+ * Arguments, layout, workspace and errors as lr_grid. */
+lr_status lr_grid_overwrite(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
+                            void *grid, double *sumwt, int64_t *counters, void *work,
+                            size_t work_bytes, lr_stream stream);
+
 /* Degridding D (Eq. ME-MOD-GRIDDED): vis = sum_t conj(Ct(o, t) phi(t)) grid[...]
  * for kept samples; flagged and dropped samples are written as 0.  No
  * weights enter the sum.  counters may be NULL. */

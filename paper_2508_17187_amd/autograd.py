@@ -51,8 +51,9 @@ class DegridOp:
         return out
 
     def grid_adjoint(self, v):
-        g = torch.zeros(self.grid_shape, dtype=self.cdt, device=v.device)
-        lr.lr_grid(self.cf, self.vis.with_(vis=v.contiguous()), self.p, g, work=self.work_g)
+        g = torch.empty(self.grid_shape, dtype=self.cdt, device=v.device)
+        lr.lr_grid_overwrite(self.cf, self.vis.with_(vis=v.contiguous()), self.p, g,
+                             work=self.work_g)
         return g
 
 

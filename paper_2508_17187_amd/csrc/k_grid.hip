@@ -112,6 +112,52 @@ struct CFElem<LR_F32_CFBF16> {
     }
 };
 
+// Raw storage words of one CF element, loaded from a byte address and
+// decoded later, so that a batch of loads is in flight before any value is
+// needed.
+template <int ST>
+struct CFRaw;
+template <>
+struct CFRaw<LR_F64> {
+    typedef double2 R;
+    static constexpr int bytes = 16;
+    __device__ static cpx<double> decode(R v, float) { return {v.x, v.y}; }
+};
+template <>
+struct CFRaw<LR_F32> {
+    typedef float2 R;
+    static constexpr int bytes = 8;
+    __device__ static cpx<float> decode(R v, float) { return {v.x, v.y}; }
+};
+template <>
+struct CFRaw<LR_F32_CF16> {
+    typedef uint32_t R;
+    static constexpr int bytes = 4;
+    __device__ static cpx<float> decode(R b, float sc) {
+        _Float16 lo, hi;
+        uint16_t l16 = (uint16_t)(b & 0xffffu), h16 = (uint16_t)(b >> 16);
+        __builtin_memcpy(&lo, &l16, 2);
+        __builtin_memcpy(&hi, &h16, 2);
+        return {(float)lo * sc, (float)hi * sc};
+    }
+};
+template <>
+struct CFRaw<LR_F32_CFBF16> {
+    typedef uint32_t R;
+    static constexpr int bytes = 4;
+    __device__ static cpx<float> decode(R b, float sc) {
+        return {__uint_as_float(b << 16) * sc, __uint_as_float(b & 0xffff0000u) * sc};
+    }
+};
+
+// Wave-uniform copies of values that are the same in every lane.
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ int64_t uni64(int64_t v) {
+    const uint32_t lo = (uint32_t)uni((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)uni((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 template <typename T>
 __device__ __forceinline__ void cmac(cpx<T> &acc, const cpx<T> &c, const cpx<T> &a) {
     acc.x = fma(c.x, a.x, acc.x);
@@ -304,22 +350,41 @@ __global__ __launch_bounds__(256) void k_presum_col(
             if (!UNIT) atomicAdd(&A[(int64_t)g * NPOL + p].y, v[p].y);
         }
     };
-    for (int b = 0; b < kColBlocks; ++b) {
+    // one step block in registers ahead: its loads are in flight while the
+    // current block is reduced
+    struct Step {
+        int g;
+        bool valid;
+        T wv[NPOL];
+        cpx<T> vv[NPOL];
+    };
+    auto fetch = [&](int b, Step &d) {
         const int64_t m = mw + b * kColT + tl;
         const int64_t j = c + m * L;
-        const bool valid = c < L && j < n_pairs;
+        d.valid = c < L && j < n_pairs;
+        d.g = d.valid ? pair_group[j] : -1;
+        for (int p = 0; p < NPOL; ++p) {
+            d.wv[p] = (T)1;
+            d.vv[p] = {(T)0, (T)0};
+        }
+        if (d.valid) {
+            if (weight) vload(weight + j * NPOL, d.wv);
+            if (SUMS && !UNIT) vload((const cpx<T> *)vis + j * NPOL, d.vv);
+        }
+    };
+    Step nxt;
+    fetch(0, nxt);
+    for (int b = 0; b < kColBlocks; ++b) {
+        const Step cur = nxt;
+        if (b + 1 < kColBlocks) fetch(b + 1, nxt);
         cpx<T> a[NPOL];
         for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
-        const int g = valid ? pair_group[j] : -1;
-        if (valid) {
-            if (g >= 0) plane = groups[g].plane;
-            T wv[NPOL];
-            cpx<T> vv[NPOL];
-            if (weight) vload(weight + j * NPOL, wv);
-            else for (int p = 0; p < NPOL; ++p) wv[p] = (T)1;
-            if (SUMS && !UNIT && g >= 0) vload((const cpx<T> *)vis + j * NPOL, vv);
+        const int g = cur.g;
+        if (cur.valid) {
+            // the channel, hence the plane, of a lane's column is fixed
+            if (g >= 0 && plane < 0) plane = groups[g].plane;
             for (int p = 0; p < NPOL; ++p) {
-                const T W = wv[p];
+                const T W = cur.wv[p];
                 if (g < 0) {
                     if (g == -2 || W == (T)0) ++flagged; else ++dropped;
                 } else if (W != (T)0) {
@@ -329,8 +394,8 @@ __global__ __launch_bounds__(256) void k_presum_col(
                         if (UNIT) {
                             a[p].x = W;
                         } else {
-                            a[p].x = W * vv[p].x;
-                            a[p].y = W * vv[p].y;
+                            a[p].x = W * cur.vv[p].x;
+                            a[p].y = W * cur.vv[p].y;
                         }
                     }
                 } else {
@@ -412,20 +477,44 @@ static void col_shape(int64_t n_pairs, int64_t L, int64_t &ncb, int64_t &blocks)
 
 // ---------------------------------------------------------------------------
 // Tile gridder.  One workgroup per chunk of (tile, group) pairs of one
-// 32 x 32 tile; thread t owns the four cells (x0 + t % 32, y0 + t / 32 + 8 j)
+// 32 x 32 tile; thread t owns the four cells (x0 + t % 32, y0 + 4 (t / 32) + j)
 // and accumulates Ct(o, t) phi(t) A_g for every group whose footprint covers
 // them, in registers.  A chunk that holds all of its tile's pairs writes the
-// tile with plain loads and stores; otherwise (and for the PSF's mirror
-// image) the flush is atomic.
+// tile with plain stores (GRID_SET: every cell; GRID_ADD: read-modify-write
+// of the touched cells); otherwise (and for the PSF's mirror image) the
+// flush is atomic.  Under GRID_SET the launch has one more workgroup per
+// tile after the chunks, which writes zeros when the tile has no pairs, so
+// the kernel writes every cell of the grid once (shared tiles are cleared
+// by the call's set-up kernel before it).
 struct TileArgs {
     const GroupMeta *groups;
-    const int32_t *tp_group, *chunk_start, *chunk_tile, *chunk_excl;
+    const int32_t *tp_group, *chunk_start, *chunk_tile, *chunk_excl, *tile_state;
     const void *A;
     void *grid;
     CFView cf;
     int32_t nx, ny, ntx, nty;
     int64_t pol_stride;   // nx * ny
+    int32_t n_chunks;
+    int32_t set;          // GRID_SET: exclusive chunks overwrite their whole tile
 };
+
+// Thread t of a 256-thread workgroup clears column t % 32 of tile `tile`.
+template <typename T, int NPOL>
+__device__ __forceinline__ void clear_tile(int tile, int32_t ntx, int32_t nty, int32_t nx,
+                                           int32_t ny, int64_t pol_stride, cpx<T> *grid) {
+    const int tx = tile % ntx;
+    const int rest = tile / ntx;
+    const int ty = rest % nty;
+    const int P = rest / nty;
+    const int x = tx * kTile + (threadIdx.x & 31);
+    if (x >= nx) return;
+    for (int r = threadIdx.x >> 5; r < kTile; r += blockDim.x >> 5) {
+        const int y = ty * kTile + r;
+        if (y >= ny) break;
+        for (int p = 0; p < NPOL; ++p)
+            grid[((int64_t)P * NPOL + p) * pol_stride + (int64_t)y * nx + x] = {(T)0, (T)0};
+    }
+}
 
 // Per-pair data of a chunk, staged in LDS once per workgroup.
 struct TileItem {
@@ -443,12 +532,29 @@ __device__ __forceinline__ void divmod_small(int t, int S, float invS, int &q, i
     if (r < 0) { --q; r += S; } else if (r >= S) { ++q; r -= S; }
 }
 
+// Items a wavefront takes per step: their kernel loads are in flight
+// together.
+constexpr int kItemBatch = 4;
+// s_waitcnt operand for vmcnt(0) with the other counters left alone
+// (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
+constexpr int kWaitVm0 = 0x0F70;
+static_assert(kChunkMax <= 64, "one ballot bit per chunk item");
+
 template <typename T, int ST, int NPOL, bool PO, bool PSF>
 __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
+    constexpr int B = kItemBatch;
+    constexpr int E = CFRaw<ST>::bytes;
+    typedef typename CFRaw<ST>::R Raw;
     __shared__ TileItem items[kChunkMax];
     __shared__ cpx<T> avs[kChunkMax * NPOL];
     __shared__ GroupMeta gms[PO ? kChunkMax : 1];
     const int c = blockIdx.x;
+    if (!PSF && c >= a.n_chunks) {      // GRID_SET: tiles without pairs
+        const int tile = c - a.n_chunks;
+        if (a.tile_state[tile] == 0)
+            clear_tile<T, NPOL>(tile, a.ntx, a.nty, a.nx, a.ny, a.pol_stride, (cpx<T> *)a.grid);
+        return;
+    }
     const int32_t s0 = a.chunk_start[c];
     const int n = a.chunk_start[c + 1] - s0;
     const int32_t key = a.chunk_tile[c];
@@ -459,6 +565,7 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     const int P = rest / a.nty;
     // thread t owns column t % 32 of rows 4 (t / 32) .. 4 (t / 32) + 3, so a
     // wavefront owns a band of 8 rows and skips footprints that miss it
+    const int lane = threadIdx.x & 63;
     const int x = tx * kTile + (threadIdx.x & 31);
     const int yb = ty * kTile + 4 * (threadIdx.x >> 5);
     const int band0 = ty * kTile + 8 * (threadIdx.x >> 6);
@@ -480,42 +587,88 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
         if (PO) gms[t] = gm;
     }
     __syncthreads();
+    // lane i tests item i against the wavefront's band: the ballot lists the
+    // items this wavefront works on (wave-uniform)
+    bool hit = false;
+    if (lane < n) {
+        const TileItem ti = items[lane];
+        hit = ti.by < band0 + 8 && ti.by + ti.S > band0;
+    }
+    uint64_t todo = __ballot(hit);
     cpx<T> acc[4][NPOL];
     for (int j = 0; j < 4; ++j)
         for (int p = 0; p < NPOL; ++p) acc[j][p] = {(T)0, (T)0};
-    int touched = 0;
-    for (int t = 0; t < n; ++t) {
-        const TileItem ti = items[t];
-        if (ti.by >= band0 + 8 || ti.by + ti.S <= band0) continue;   // wave-uniform
-        const int dx = x - ti.bx;
-        const bool inx = (unsigned)dx < (unsigned)ti.S;
-        cpx<T> cv[4];
-        int dys[4];
-        int inm = 0;
-        // the four cell loads are issued together, predicated instead of branched
-        for (int j = 0; j < 4; ++j) {
-            const int dy = yb + j - ti.by;
-            dys[j] = dy;
-            const bool in = inx && (unsigned)dy < (unsigned)ti.S;
-            inm |= in ? (1 << j) : 0;
-            cv[j] = CFElem<ST>::load(a.cf.table, ti.cf_off + (in ? dy * ti.S + dx : 0), ti.sc);
+    const char *table = (const char *)a.cf.table;
+    while (todo) {
+        int idx[B];
+        for (int b = 0; b < B; ++b) {
+            idx[b] = todo ? __builtin_ctzll(todo) : -1;
+            todo &= todo - 1;
         }
-        for (int j = 0; j < 4; ++j) {
-            const bool in = (inm >> j) & 1;
-            if (!in) cv[j] = {(T)0, (T)0};
-            if (ti.conj) cv[j].y = -cv[j].y;
-            if (PO && in) cv[j] = cmul(cv[j], phasor<T>(gms[t], dx - ti.h, dys[j] - ti.h, a.cf.O));
+        Raw cv[B][4];
+        bool ok[B][4];
+        int dxs[B], rs[B];
+        float scs[B];
+        // the kernel loads of the whole batch are issued before any is used;
+        // an item's fields are wave-uniform, so its sub-kernel base address
+        // is scalar and a lane only adds its 32-bit offset; cells outside
+        // the footprint neither load nor accumulate
+        for (int b = 0; b < B; ++b) {
+            for (int j = 0; j < 4; ++j) ok[b][j] = false;
+            dxs[b] = rs[b] = 0;
+            if (idx[b] < 0) continue;
+            const TileItem ti = items[idx[b]];
+            const int S = uni(ti.S);
+            const char *base = table + uni64(ti.cf_off) * E;
+            scs[b] = ti.sc;
+            const int dx = x - uni(ti.bx);
+            const int r = yb - uni(ti.by);
+            dxs[b] = dx;
+            rs[b] = r;
+            const bool cin = (unsigned)dx < (unsigned)S;
+            const unsigned SS = (unsigned)(S * S);
+            int off = __mul24(r, S) + dx;  // element offset of the lane's first row
+            for (int j = 0; j < 4; ++j, off += S) {
+                ok[b][j] = cin && (unsigned)off < SS;
+                if (ok[b][j]) cv[b][j] = *(const Raw *)(base + (uint32_t)off * (uint32_t)E);
+            }
         }
-        for (int p = 0; p < NPOL; ++p) {
-            const cpx<T> av = avs[t * NPOL + p];
-            for (int j = 0; j < 4; ++j) cmac(acc[j][p], cv[j], av);
+        for (int b = 0; b < B; ++b) {
+            if (idx[b] < 0) continue;
+            const int t = idx[b];
+            const bool cj = uni(items[t].conj) != 0;
+            cpx<T> av[NPOL];
+            for (int p = 0; p < NPOL; ++p) av[p] = avs[t * NPOL + p];
+            for (int j = 0; j < 4; ++j) {
+                if (!ok[b][j]) continue;
+                cpx<T> cw = CFRaw<ST>::decode(cv[b][j], scs[b]);
+                if (cj) cw.y = -cw.y;
+                if (PO) {
+                    const int h = items[t].h;
+                    cw = cmul(cw, phasor<T>(gms[t], dxs[b] - h, rs[b] + j - h, a.cf.O));
+                }
+                for (int p = 0; p < NPOL; ++p) cmac(acc[j][p], cw, av[p]);
+            }
         }
-        touched |= inm;
+        // every load of the batch has landed (rows that no lane needed were
+        // skipped): saying so lets the next batch reuse their registers
+        // without a wait in front of each load
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
     }
     T *grid = (T *)a.grid;
+    const bool set = excl && a.set;
     for (int j = 0; j < 4; ++j) {
-        if (!(touched & (1 << j))) continue;
         const int y = yb + j;
+        if (set) {
+            if (x >= a.nx || y >= a.ny) continue;
+        } else {
+            // cells that received nothing are left alone (adding an exact
+            // zero would not change them)
+            bool any = false;
+            for (int p = 0; p < NPOL; ++p)
+                any |= acc[j][p].x != (T)0 || acc[j][p].y != (T)0;
+            if (!any) continue;
+        }
         for (int p = 0; p < NPOL; ++p) {
             const int64_t base = ((int64_t)P * NPOL + p) * a.pol_stride;
             T *q = grid + 2 * (base + (int64_t)y * a.nx + x);
@@ -525,6 +678,9 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
                 atomicAdd(q + 1, (T)0.5 * acc[j][p].y);
                 atomicAdd(m, (T)0.5 * acc[j][p].x);
                 atomicAdd(m + 1, -(T)0.5 * acc[j][p].y);
+            } else if (set) {
+                q[0] = acc[j][p].x;
+                q[1] = acc[j][p].y;
             } else if (excl) {
                 q[0] += acc[j][p].x;
                 q[1] += acc[j][p].y;
@@ -532,6 +688,38 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
                 atomicAdd(q, acc[j][p].x);
                 atomicAdd(q + 1, acc[j][p].y);
             }
+        }
+    }
+}
+
+// Set-up of a gridding call in one launch: the first n_shared workgroups
+// clear the shared tiles (GRID_SET), the rest zero up to three word spans
+// (group sums, sums of weights, counters), four 8-byte words per thread.
+struct SetupArgs {
+    uint64_t *z[3];
+    int64_t zw[3];            // words per span
+    const int32_t *shared;
+    int32_t n_shared, ntx, nty, nx, ny;
+    int64_t pol_stride;
+    void *grid;
+};
+
+template <typename T, int NPOL>
+__global__ __launch_bounds__(256) void k_grid_setup(SetupArgs a) {
+    if ((int)blockIdx.x < a.n_shared) {
+        clear_tile<T, NPOL>(a.shared[blockIdx.x], a.ntx, a.nty, a.nx, a.ny, a.pol_stride,
+                            (cpx<T> *)a.grid);
+        return;
+    }
+    int64_t w = ((int64_t)(blockIdx.x - a.n_shared) * blockDim.x + threadIdx.x) * 4;
+    for (int i = 0; i < 4; ++i, ++w) {
+        int64_t r = w;
+        for (int k = 0; k < 3; ++k) {
+            if (r < a.zw[k]) {
+                a.z[k][r] = 0;
+                break;
+            }
+            r -= a.zw[k];
         }
     }
 }
@@ -547,46 +735,77 @@ struct DegridArgs {
     int64_t pol_stride;
 };
 
+// One wavefront per group: lanes walk the footprint taps in row-major order,
+// four taps per lane in flight; the sub-kernel and the footprint's corner
+// cell (per pol) are scalar base addresses and a lane carries 32-bit
+// offsets, advanced by 64 taps at a time without division.
 template <typename T, int ST, int NPOL, bool PO>
 __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
+    constexpr int E = CFRaw<ST>::bytes;
+    typedef typename CFRaw<ST>::R Raw;
     const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    // consecutive groups (same plane, neighbouring footprints) run side by
+    // side across the XCDs, which share the last-level cache
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + uni(threadIdx.x >> 6);
     if (g >= a.n_groups) return;
     const GroupMeta gm = a.groups[g];
-    const int h = a.cf.h[gm.k];
+    const int k = uni(gm.k);
+    const int h = uni(a.cf.h[k]);
     const int S = 2 * h + 1;
     const int SS = S * S;
-    const float invS = 1.0f / (float)S;
-    const float sc = a.cf.scale[gm.fg * a.cf.n_w + gm.k];
-    const T *grid = (const T *)a.grid;
-    const int64_t base = gm.cell - (int64_t)h * a.nx - h;     // cell of tap (0, 0), pol 0
+    const float sc = a.cf.scale[uni(gm.fg) * a.cf.n_w + k];
+    const bool cj = uni(gm.conj) != 0;
+    const char *cfb = (const char *)a.cf.table + uni64(gm.cf_off) * E;
+    // corner cell (tap (0, 0)) of pol 0
+    const int64_t corner = uni64(gm.cell) - (int64_t)h * a.nx - h;
+    const int64_t pstride = a.pol_stride * (int64_t)(2 * sizeof(T));
+    // one scalar base per pol (its byte offset made opaque, so that a lane's
+    // offset is added to it rather than folded into 64-bit vector arithmetic)
+    const char *gbp[NPOL];
+    for (int p = 0; p < NPOL; ++p)
+        gbp[p] = (const char *)a.grid + uni64(corner * (int64_t)(2 * sizeof(T)) + p * pstride);
+    const int row = a.nx * (int)(2 * sizeof(T));          // bytes per grid row
+    // lane's first tap and the per-step advance of 64 taps
+    const int dty = 64 / S, dtx = 64 - dty * S;
+    int ty = lane / S, tx = lane - (lane / S) * S;
+    int goff = ty * row + tx * (int)(2 * sizeof(T));
     cpx<T> sum[NPOL];
     for (int p = 0; p < NPOL; ++p) sum[p] = {(T)0, (T)0};
-    // four taps per lane per step, their loads issued together
     for (int t0 = 0; t0 < SS; t0 += 256) {
-        cpx<T> cv[4], gv[4][NPOL];
-        int tys[4], txs[4];
+        Raw cr[4];
+        cpx<T> gv[4][NPOL];
+        bool ok[4];
+        int txs[4], tys[4];
         for (int u = 0; u < 4; ++u) {
             const int tap = t0 + u * 64 + lane;
-            const bool in = tap < SS;
-            int ty, tx;
-            divmod_small(in ? tap : 0, S, invS, ty, tx);
-            tys[u] = ty;
+            ok[u] = tap < SS;
             txs[u] = tx;
-            cv[u] = CFElem<ST>::load(a.cf.table, gm.cf_off + (in ? tap : 0), sc);
-            if (!in) cv[u] = {(T)0, (T)0};
-            const int64_t cell = base + (int64_t)ty * a.nx + tx;
-            for (int p = 0; p < NPOL; ++p) {
-                const T *q = grid + 2 * (cell + p * a.pol_stride);
-                gv[u][p] = {q[0], q[1]};
+            tys[u] = ty;
+            if (ok[u]) {
+                cr[u] = *(const Raw *)(cfb + (uint32_t)tap * (uint32_t)E);
+                for (int p = 0; p < NPOL; ++p) {
+                    const T *q = (const T *)(gbp[p] + (uint32_t)goff);
+                    gv[u][p] = {q[0], q[1]};
+                }
+            }
+            // advance by 64 taps
+            tx += dtx;
+            ty += dty;
+            goff += dty * row + dtx * (int)(2 * sizeof(T));
+            if (tx >= S) {
+                tx -= S;
+                ++ty;
+                goff += row - S * (int)(2 * sizeof(T));
             }
         }
         for (int u = 0; u < 4; ++u) {
-            if (gm.conj) cv[u].y = -cv[u].y;
-            if (PO && t0 + u * 64 + lane < SS)
-                cv[u] = cmul(cv[u], phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
-            for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv[u], gv[u][p]);
+            if (!ok[u]) continue;
+            cpx<T> cv = CFRaw<ST>::decode(cr[u], sc);
+            if (cj) cv.y = -cv.y;
+            if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
+            for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
         }
+        __builtin_amdgcn_s_waitcnt(kWaitVm0);
     }
     cpx<T> *out = (cpx<T> *)a.Vg;
     for (int p = 0; p < NPOL; ++p) {
@@ -623,11 +842,6 @@ static hipError_t presum_t(const lr_plan *P, const VisArgs &v, void *A, double *
     const T *vis = (const T *)v.vis;
     const T *wt = (const T *)v.weight;
     long long *cnt = (long long *)counters;
-    if (sums) {
-        hipError_t e = launch_zero(A, (size_t)std::max<int64_t>(P->n_groups, 1) * NPOL *
-                                          sizeof(cpx<T>), s);
-        if (e != hipSuccess) return e;
-    }
     if (P->period > 0) {
         int64_t ncb, nb;
         col_shape(P->n_pairs, P->period, ncb, nb);
@@ -687,9 +901,9 @@ hipError_t launch_counts(const lr_plan *P, const void *weight, int precision, in
 }
 
 template <typename T, int ST, int NPOL>
-static hipError_t grid_t(const TileArgs &ta, int64_t n_chunks, bool po, bool psf,
+static hipError_t grid_t(const TileArgs &ta, int64_t n_blocks, bool po, bool psf,
                          hipStream_t s) {
-    dim3 grd((unsigned)n_chunks), blk(256);
+    dim3 grd((unsigned)n_blocks), blk(256);
     if (po) {
         if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, true>), grd, blk, 0, s, ta);
         else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, false>), grd, blk, 0, s, ta);
@@ -701,29 +915,69 @@ static hipError_t grid_t(const TileArgs &ta, int64_t n_chunks, bool po, bool psf
 }
 
 template <typename T, int ST>
-static hipError_t grid_np(const TileArgs &ta, int64_t n_chunks, int npol, bool po, bool psf,
+static hipError_t grid_np(const TileArgs &ta, int64_t n_blocks, int npol, bool po, bool psf,
                           hipStream_t s) {
     switch (npol) {
-        case 1: return grid_t<T, ST, 1>(ta, n_chunks, po, psf, s);
-        case 2: return grid_t<T, ST, 2>(ta, n_chunks, po, psf, s);
-        default: return grid_t<T, ST, 4>(ta, n_chunks, po, psf, s);
+        case 1: return grid_t<T, ST, 1>(ta, n_blocks, po, psf, s);
+        case 2: return grid_t<T, ST, 2>(ta, n_blocks, po, psf, s);
+        default: return grid_t<T, ST, 4>(ta, n_blocks, po, psf, s);
     }
 }
 
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
-                       int precision, int32_t npol, int32_t nx, int32_t ny, int32_t psf,
+                       int precision, int32_t npol, int32_t nx, int32_t ny, int32_t mode,
                        hipStream_t s) {
-    if (P->n_chunks == 0) return hipSuccess;
-    TileArgs ta{P->groups, P->tp_group, P->chunk_start, P->chunk_tile, P->chunk_excl, A, grid,
-                cf, nx, ny, (nx + kTile - 1) / kTile, (ny + kTile - 1) / kTile,
-                (int64_t)nx * ny};
+    const bool set = mode == GRID_SET;
+    // GRID_SET: one more workgroup per tile clears the tiles without pairs
+    const int64_t nc = P->n_chunks + (set ? P->n_tiles : 0);
+    if (nc == 0) return hipSuccess;
+    TileArgs ta{P->groups, P->tp_group, P->chunk_start, P->chunk_tile, P->chunk_excl,
+                P->tile_state, A, grid, cf, nx, ny, (nx + kTile - 1) / kTile,
+                (ny + kTile - 1) / kTile, (int64_t)nx * ny, (int32_t)P->n_chunks,
+                set ? 1 : 0};
     bool po = P->po != 0;
-    int64_t nc = P->n_chunks;
+    bool psf = mode == GRID_PSF;
     switch (precision) {
         case LR_F64: return grid_np<double, LR_F64>(ta, nc, npol, po, psf, s);
         case LR_F32: return grid_np<float, LR_F32>(ta, nc, npol, po, psf, s);
         case LR_F32_CF16: return grid_np<float, LR_F32_CF16>(ta, nc, npol, po, psf, s);
         default: return grid_np<float, LR_F32_CFBF16>(ta, nc, npol, po, psf, s);
+    }
+}
+
+template <typename T, int NPOL>
+static hipError_t setup_t(const SetupArgs &sa, int64_t n_blocks, hipStream_t s) {
+    hipLaunchKernelGGL((k_grid_setup<T, NPOL>), dim3((unsigned)n_blocks), dim3(256), 0, s, sa);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *sumwt,
+                             size_t sumwt_bytes, int64_t *counters, void *grid,
+                             int precision, int32_t npol, int32_t nx, int32_t ny, bool set,
+                             hipStream_t s) {
+    SetupArgs sa;
+    sa.z[0] = (uint64_t *)A;
+    sa.zw[0] = A ? (int64_t)(a_bytes / 8) : 0;
+    sa.z[1] = (uint64_t *)sumwt;
+    sa.zw[1] = sumwt ? (int64_t)(sumwt_bytes / 8) : 0;
+    sa.z[2] = (uint64_t *)counters;
+    sa.zw[2] = counters ? 3 : 0;
+    sa.shared = P->shared_tiles;
+    sa.n_shared = set ? (int32_t)P->n_shared : 0;
+    sa.ntx = (nx + kTile - 1) / kTile;
+    sa.nty = (ny + kTile - 1) / kTile;
+    sa.nx = nx;
+    sa.ny = ny;
+    sa.pol_stride = (int64_t)nx * ny;
+    sa.grid = grid;
+    const int64_t words = sa.zw[0] + sa.zw[1] + sa.zw[2];
+    const int64_t n_blocks = sa.n_shared + (words + 1023) / 1024;
+    if (n_blocks == 0) return hipSuccess;
+    const bool f64 = precision == LR_F64;
+    switch (npol) {
+        case 1: return f64 ? setup_t<double, 1>(sa, n_blocks, s) : setup_t<float, 1>(sa, n_blocks, s);
+        case 2: return f64 ? setup_t<double, 2>(sa, n_blocks, s) : setup_t<float, 2>(sa, n_blocks, s);
+        default: return f64 ? setup_t<double, 4>(sa, n_blocks, s) : setup_t<float, 4>(sa, n_blocks, s);
     }
 }
 

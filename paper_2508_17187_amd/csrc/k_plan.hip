@@ -249,10 +249,28 @@ __global__ void k_tile_fill(const GroupMeta *groups, int64_t n_groups, const int
         }
 }
 
+// Chunk heads: each tile's run of (tile, group) pairs (keys sorted by tile)
+// is cut into ceil(run / per) chunks of near-equal size, so a tile with at
+// most `per` pairs is one exclusive chunk.
 __global__ void k_chunk_flags(const uint32_t *keys, int64_t n, int32_t per, int32_t *flags) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    flags[i] = (i == 0 || keys[i] != keys[i - 1] || (i % per) == 0) ? 1 : 0;
+    const uint32_t k = keys[i];
+    int64_t lo = 0, hi = i;             // first index of the run
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] < k) lo = mid + 1; else hi = mid;
+    }
+    const int64_t start = lo;
+    lo = i + 1;
+    hi = n;                             // one past its last index
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (keys[mid] <= k) lo = mid + 1; else hi = mid;
+    }
+    const int64_t run = lo - start, local = i - start;
+    const int64_t nc = (run + per - 1) / per;
+    flags[i] = (local == 0 || local * nc / run != (local - 1) * nc / run) ? 1 : 0;
 }
 
 __global__ void k_chunk_build(const uint32_t *keys, const int32_t *flags, const int32_t *cidx,
@@ -279,6 +297,24 @@ __global__ void k_chunk_excl(const uint32_t *keys, int32_t *chunk_start, int64_t
 
 __global__ void k_chunk_end(int32_t *chunk_start, int64_t n_chunks, int64_t n) {
     if (threadIdx.x == 0) chunk_start[n_chunks] = (int32_t)n;
+}
+
+// Tile ownership: 1 when one exclusive chunk holds all of the tile's pairs,
+// 2 when several chunks share it (tile_state is zeroed beforehand; the
+// chunks of a shared tile all store the same value).
+__global__ void k_tile_state(const int32_t *chunk_tile, const int32_t *chunk_excl,
+                             int64_t n_chunks, int32_t *tile_state) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    tile_state[chunk_tile[c]] = chunk_excl[c] ? 1 : 2;
+}
+
+// Compact list of the shared tiles (any order).
+__global__ void k_shared_list(const int32_t *tile_state, int64_t n_tiles, int32_t *list,
+                              int32_t *count) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles || tile_state[t] != 2) return;
+    list[atomicAdd(count, 1)] = (int32_t)t;
 }
 
 // Group of every pair in natural (row, channel) order: >= 0 kept, -1
@@ -346,7 +382,11 @@ int64_t max_tiles_per_group(int32_t h_max) {
     return span * span;
 }
 
-PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max) {
+int64_t tile_count(int32_t nx, int32_t ny, int32_t nplane) {
+    return (int64_t)nplane * ((nx + kTile - 1) / kTile) * ((ny + kTile - 1) / kTile);
+}
+
+PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max, int64_t n_tiles) {
     PlanLayout L;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t o = off; off += align256(bytes); return o; };
@@ -362,6 +402,8 @@ PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max) {
     L.chunk_start = take(sizeof(int32_t) * (ntp + 1));
     L.chunk_tile = take(sizeof(int32_t) * ntp);
     L.chunk_excl = take(sizeof(int32_t) * ntp);
+    L.tile_state = take(sizeof(int32_t) * std::max<int64_t>(n_tiles, 1));
+    L.shared_tiles = take(sizeof(int32_t) * std::max<int64_t>(n_tiles, 1));
     L.persistent = off;
     // transient
     L.keys_a = take(sizeof(uint64_t) * std::max(n, ntp));
@@ -403,7 +445,13 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->chunk_start = (int32_t *)(buf + L.chunk_start);
     P->chunk_tile = (int32_t *)(buf + L.chunk_tile);
     P->chunk_excl = (int32_t *)(buf + L.chunk_excl);
+    P->tile_state = (int32_t *)(buf + L.tile_state);
+    P->n_tiles = tile_count(g.nx, g.ny, g.nplane);
+    P->shared_tiles = (int32_t *)(buf + L.shared_tiles);
+    P->n_shared = 0;
     P->n_kept = P->n_groups = P->n_tile_pairs = P->n_chunks = P->taps = 0;
+    if ((e = launch_zero(P->tile_state, sizeof(int32_t) * P->n_tiles, s)) != hipSuccess)
+        return e;
     if (n == 0) return hipSuccess;
 
     if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
@@ -479,6 +527,15 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     hipLaunchKernelGGL(k_chunk_excl, dim3(blocks(nch, 256)), dim3(256), 0, s, tk_b,
                        P->chunk_start, nch, ntp, P->chunk_excl);
     hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(64), 0, s, P->chunk_start, nch, ntp);
+    hipLaunchKernelGGL(k_tile_state, dim3(blocks(nch, 256)), dim3(256), 0, s, P->chunk_tile,
+                       P->chunk_excl, nch, P->tile_state);
+    if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_shared_list, dim3(blocks(P->n_tiles, 256)), dim3(256), 0, s,
+                       P->tile_state, P->n_tiles, P->shared_tiles, (int32_t *)counter);
+    int32_t n_shared = 0;
+    (void)hipMemcpyAsync(&n_shared, counter, 4, hipMemcpyDeviceToHost, s);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    P->n_shared = n_shared;
     if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_taps, dim3(blocks(ng, 256)), dim3(256), 0, s, P->groups, ng, cf.h,
                        counter);

@@ -301,7 +301,8 @@ KeyLayout key_layout(const lr_cf *cf, const lr_vis *v, bool po, int32_t &merged)
 }
 
 size_t plan_total(const lr_cf *cf, const lr_vis *v) {
-    return plan_layout((int64_t)v->nrow * v->nchan, v->nchan, h_max_of(cf)).total;
+    return plan_layout((int64_t)v->nrow * v->nchan, v->nchan, h_max_of(cf),
+                       tile_count(cf->grid.nx, cf->grid.ny, cf->grid.nplane)).total;
 }
 
 lr_status plan_matches(const lr_plan *P, const lr_cf *cf, const lr_vis *v, int psf) {
@@ -324,7 +325,8 @@ lr_status plan_matches(const lr_plan *P, const lr_cf *cf, const lr_vis *v, int p
 lr_status build_plan(const lr_cf *cf, const lr_vis *v, int psf, void *buf, size_t bytes,
                      hipStream_t s, lr_plan *P) {
     int64_t n_pairs = (int64_t)v->nrow * v->nchan;
-    PlanLayout L = plan_layout(n_pairs, v->nchan, h_max_of(cf));
+    PlanLayout L = plan_layout(n_pairs, v->nchan, h_max_of(cf),
+                               tile_count(cf->grid.nx, cf->grid.ny, cf->grid.nplane));
     if (!buf && L.total) return fail(LR_E_ARG, "plan buffer is NULL");
     if (bytes < L.total) return fail(LR_E_WORKSPACE, "plan needs %zu bytes, got %zu", L.total, bytes);
     bool po = v->ant1 != nullptr;
@@ -413,7 +415,9 @@ size_t lr_workspace_bytes(int op, const lr_cf_spec *spec, const lr_grid_spec *gr
     if (op == LR_OP_CF_BUILD) return cf_work_bytes(G.M, spec->oversample, G.hmax);
     if (!vis) { fail(LR_E_ARG, "vis descriptor is NULL"); return 0; }
     int64_t n_pairs = (int64_t)vis->nrow * vis->nchan;
-    size_t plan = vis->plan ? 0 : al256(plan_layout(n_pairs, vis->nchan, G.hmax).total);
+    size_t plan = vis->plan ? 0 : al256(plan_layout(n_pairs, vis->nchan, G.hmax,
+                                                    tile_count(grid->nx, grid->ny,
+                                                               grid->nplane)).total);
     int64_t n_groups = vis->plan ? vis->plan->n_groups : n_pairs;
     size_t per = 0;
     if (op == LR_OP_GRID || op == LR_OP_PSF || op == LR_OP_DEGRID)
@@ -537,7 +541,8 @@ lr_status lr_set_profile_events(void *start, void *stop) {
 
 static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
                              void *grid, double *sumwt, int64_t *counters, void *work,
-                             size_t work_bytes, lr_stream stream, int psf) {
+                             size_t work_bytes, lr_stream stream, int mode) {
+    const int psf = mode == GRID_PSF ? 1 : 0;
     lr_status st = check_vis(cf, vis, !psf, true);
     if (st != LR_OK) return st;
     if ((st = check_precision(cf, precision)) != LR_OK) return st;
@@ -557,11 +562,19 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
     void *A = (char *)work + used;
     VisArgs va{vis->vis, vis->weight, vis->npol, psf ? 1 : 0};
     ProfileScope prof(s);
-    hipError_t e = launch_presum(P, va, precision, A, sumwt, counters, cf->grid.nplane, s);
+    // group sums start at zero; GRID_SET replaces the outputs, so it also
+    // clears sumwt, the counters and the shared tiles
+    const bool set = mode == GRID_SET;
+    hipError_t e = launch_grid_setup(
+        P, A, (size_t)P->n_groups * vis->npol * cplx_bytes(precision), set ? sumwt : nullptr,
+        sizeof(double) * cf->grid.nplane * vis->npol, set ? counters : nullptr, grid, precision,
+        vis->npol, cf->grid.nx, cf->grid.ny, set, s);
+    if (e == hipSuccess)
+        e = launch_presum(P, va, precision, A, sumwt, counters, cf->grid.nplane, s);
     if (e == hipSuccess) {
         prof.begin();
         e = launch_grid(P, view_of(cf), A, grid, precision, vis->npol, cf->grid.nx,
-                        cf->grid.ny, psf, s);
+                        cf->grid.ny, mode, s);
         prof.end();
     }
     if (e != hipSuccess) return dev_fail(e, psf ? "psf" : "grid");
@@ -571,14 +584,22 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
 lr_status lr_grid(const lr_cf *cf, const lr_vis *vis, lr_precision precision, void *grid,
                   double *sumwt, int64_t *counters, void *work, size_t work_bytes,
                   lr_stream stream) {
-    return grid_common(cf, vis, precision, grid, sumwt, counters, work, work_bytes, stream, 0);
+    return grid_common(cf, vis, precision, grid, sumwt, counters, work, work_bytes, stream,
+                       GRID_ADD);
+}
+
+lr_status lr_grid_overwrite(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
+                            void *grid, double *sumwt, int64_t *counters, void *work,
+                            size_t work_bytes, lr_stream stream) {
+    return grid_common(cf, vis, precision, grid, sumwt, counters, work, work_bytes, stream,
+                       GRID_SET);
 }
 
 lr_status lr_make_psf(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
                       void *psf_grid, double *sumwt, int64_t *counters, void *work,
                       size_t work_bytes, lr_stream stream) {
     return grid_common(cf, vis, precision, psf_grid, sumwt, counters, work, work_bytes, stream,
-                       1);
+                       GRID_PSF);
 }
 
 lr_status lr_degrid(const lr_cf *cf, lr_vis *vis, lr_precision precision, const void *grid,

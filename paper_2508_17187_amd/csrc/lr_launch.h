@@ -16,7 +16,7 @@ struct KeyLayout {
 
 struct PlanLayout {
     size_t chan, order, gidx, pair_group, group_start, groups, tp_group, chunk_start, chunk_tile,
-        chunk_excl, persistent;
+        chunk_excl, tile_state, shared_tiles, persistent;
     size_t keys_a, keys_b, vals_a, flags, scan, counter, temp;
     int64_t max_tp;
     size_t total;
@@ -29,7 +29,8 @@ hipError_t launch_debug_map(int64_t nrow, int32_t nchan, const double *uvw,
                             hipStream_t s);
 size_t sort_temp_bytes(int64_t n, int64_t n_tp);
 int64_t max_tiles_per_group(int32_t h_max);
-PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max);
+PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max, int64_t n_tiles);
+int64_t tile_count(int32_t nx, int32_t ny, int32_t nplane);
 hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const double *uvw,
                              const ChanConst *d_cc, const MapGeom &g, const KeyLayout &kl,
                              const CFView &cf, const int32_t *ant1, const int32_t *ant2,
@@ -54,14 +55,25 @@ struct VisArgs {
     int32_t unit_vis;      // PSF: visibilities taken as 1
 };
 
-// presum: per group A[g][pol] = sum W V over its pairs; counters and sumwt
+// presum: per group A[g][pol] += sum W V over its pairs (A zeroed by
+// launch_grid_setup); counters and sumwt
 hipError_t launch_presum(const lr_plan *P, const VisArgs &v, int precision, void *A,
                          double *sumwt, int64_t *counters, int32_t nplane, hipStream_t s);
 hipError_t launch_counts(const lr_plan *P, const void *weight, int precision, int32_t npol,
                          double *sumwt, int64_t *counters, int32_t nplane, hipStream_t s);
+// mode: GRID_ADD (grid +=), GRID_PSF (grid += half the mirror pair), GRID_SET
+// (grid =, every cell written; zero_tiles must have run on the same stream)
+enum { GRID_ADD = 0, GRID_PSF = 1, GRID_SET = 2 };
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
-                       int precision, int32_t npol, int32_t nx, int32_t ny, int32_t psf,
+                       int precision, int32_t npol, int32_t nx, int32_t ny, int32_t mode,
                        hipStream_t s);
+// Set-up of a gridding call, one launch: zero the group sums A (a_bytes)
+// and, when given, sumwt and counters; under GRID_SET also the tiles that
+// several chunks share (they are then added to atomically).
+hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *sumwt,
+                             size_t sumwt_bytes, int64_t *counters, void *grid,
+                             int precision, int32_t npol, int32_t nx, int32_t ny, bool set,
+                             hipStream_t s);
 hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
                          int precision, int32_t npol, int32_t nx, int32_t ny, hipStream_t s);
 hipError_t launch_expand(const lr_plan *P, const void *Vg, void *vis, const void *weight,

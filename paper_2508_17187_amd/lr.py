@@ -72,6 +72,8 @@ EXPORTS = {
     "lr_set_profile_events": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lr_grid": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                           C.c_void_p, C.c_size_t, C.c_void_p]),
+    "lr_grid_overwrite": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                    C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "lr_degrid": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_size_t, C.c_void_p]),
     "lr_make_psf": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
@@ -304,6 +306,15 @@ def lr_grid(cf, vis, precision, grid, sumwt=None, counters=None, work=None, stre
     d = vis.desc()
     _check(lib().lr_grid(cf.handle, C.byref(d), precision, _ptr(grid), _ptr(sumwt),
                          _ptr(counters), _ptr(work), work.numel(), _stream(stream)))
+    return work
+
+
+def lr_grid_overwrite(cf, vis, precision, grid, sumwt=None, counters=None, work=None,
+                      stream=None):
+    work = _work(LR_OP_GRID, cf, vis, precision, work)
+    d = vis.desc()
+    _check(lib().lr_grid_overwrite(cf.handle, C.byref(d), precision, _ptr(grid), _ptr(sumwt),
+                                   _ptr(counters), _ptr(work), work.numel(), _stream(stream)))
     return work
 
 

@@ -319,9 +319,9 @@ class GPUExecutor:
             v = lr.Vis(uvw, pl["freq"], pl["chan_plane"], None, weight=wt, npol=g.npol)
             if job.op == "grid":
                 v.vis = torch.as_tensor(pl["vis"]).to(self.dev, dtype=self.cplx, non_blocking=True)
-                grid = torch.zeros((g.nplane, g.npol, g.ny, g.nx), dtype=self.cplx,
+                grid = torch.empty((g.nplane, g.npol, g.ny, g.nx), dtype=self.cplx,
                                    device=self.dev)
-                lr.lr_grid(cf, v, self.p, grid, stream=s)
+                lr.lr_grid_overwrite(cf, v, self.p, grid, stream=s)
                 out = grid.cpu()
             else:
                 grid = torch.as_tensor(pl["grid"]).to(self.dev, dtype=self.cplx,
