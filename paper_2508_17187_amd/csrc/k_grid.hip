@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_presum(
 // loads at once and 8 consecutive pairs are contiguous; a 3-step segmented
 // shuffle reduces along the steps and the last lane of each run of equal
 // groups adds it to A with one atomic.
-constexpr int kColW = 8, kColT = 8, kColBlocks = 8;
+constexpr int kColW = 8, kColT = 8, kColBlocks = 16;
 
 template <typename T, int NPOL, bool UNIT, bool SUMS>
 __global__ __launch_bounds__(256) void k_presum_col(
@@ -538,7 +538,8 @@ constexpr int kItemBatch = 4;
 // s_waitcnt operand for vmcnt(0) with the other counters left alone
 // (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int kWaitVm0 = 0x0F70;
-static_assert(kChunkMax <= 64, "one ballot bit per chunk item");
+// items of a chunk as ballot bits, 64 per word
+constexpr int kMaskWords = (kChunkMax + 63) / 64;
 
 template <typename T, int ST, int NPOL, bool PO, bool PSF>
 __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
@@ -589,22 +590,37 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     __syncthreads();
     // lane i tests item i against the wavefront's band: the ballot lists the
     // items this wavefront works on (wave-uniform)
-    bool hit = false;
-    if (lane < n) {
-        const TileItem ti = items[lane];
-        hit = ti.by < band0 + 8 && ti.by + ti.S > band0;
+    uint64_t todo[kMaskWords];
+    for (int w = 0; w < kMaskWords; ++w) {
+        bool hit = false;
+        const int it = w * 64 + lane;
+        if (it < n) {
+            const TileItem ti = items[it];
+            hit = ti.by < band0 + 8 && ti.by + ti.S > band0;
+        }
+        todo[w] = __ballot(hit);
     }
-    uint64_t todo = __ballot(hit);
+    auto pending = [&]() {
+        uint64_t any = 0;
+        for (int w = 0; w < kMaskWords; ++w) any |= todo[w];
+        return any != 0;
+    };
+    auto next = [&]() {
+        for (int w = 0; w < kMaskWords; ++w)
+            if (todo[w]) {
+                const int i = __builtin_ctzll(todo[w]);
+                todo[w] &= todo[w] - 1;
+                return w * 64 + i;
+            }
+        return -1;
+    };
     cpx<T> acc[4][NPOL];
     for (int j = 0; j < 4; ++j)
         for (int p = 0; p < NPOL; ++p) acc[j][p] = {(T)0, (T)0};
     const char *table = (const char *)a.cf.table;
-    while (todo) {
+    while (pending()) {
         int idx[B];
-        for (int b = 0; b < B; ++b) {
-            idx[b] = todo ? __builtin_ctzll(todo) : -1;
-            todo &= todo - 1;
-        }
+        for (int b = 0; b < B; ++b) idx[b] = next();
         Raw cv[B][4];
         bool ok[B][4];
         int dxs[B], rs[B];

@@ -249,28 +249,41 @@ __global__ void k_tile_fill(const GroupMeta *groups, int64_t n_groups, const int
         }
 }
 
-// Chunk heads: each tile's run of (tile, group) pairs (keys sorted by tile)
-// is cut into ceil(run / per) chunks of near-equal size, so a tile with at
-// most `per` pairs is one exclusive chunk.
-__global__ void k_chunk_flags(const uint32_t *keys, int64_t n, int32_t per, int32_t *flags) {
+// Work of a (tile, group) pair: the cells its footprint covers in the tile.
+__global__ void k_pair_cost(const uint32_t *keys, const int32_t *tp_group,
+                            const GroupMeta *groups, const int32_t *h, int32_t ntx,
+                            int32_t nty, int64_t n, int32_t *cost) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    const uint32_t key = keys[i];
+    const int tx = (int)(key % (uint32_t)ntx);
+    const int ty = (int)((key / (uint32_t)ntx) % (uint32_t)nty);
+    const GroupMeta gm = groups[tp_group[i]];
+    const int hh = h[gm.k];
+    const int cx = min(gm.pu + hh + 1, (tx + 1) * kTile) - max(gm.pu - hh, tx * kTile);
+    const int cy = min(gm.pv + hh + 1, (ty + 1) * kTile) - max(gm.pv - hh, ty * kTile);
+    cost[i] = max(cx, 0) * max(cy, 0);
+}
+
+// Chunk heads: the first thread of each tile's run of (tile, group) pairs
+// (keys sorted by tile) walks the run and opens a new chunk when the current
+// one holds `per` pairs or its pairs cover more than `cmax` cells in all, so
+// that no workgroup of the gridder gets far more work than the others.  A
+// tile that fits one chunk is owned exclusively.
+__global__ void k_chunk_flags(const uint32_t *keys, const int32_t *cost, int64_t n,
+                              int32_t per, int32_t cmax, int32_t *flags) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n || (i > 0 && keys[i] == keys[i - 1])) return;
     const uint32_t k = keys[i];
-    int64_t lo = 0, hi = i;             // first index of the run
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] < k) lo = mid + 1; else hi = mid;
+    int count = 0, work = 0;
+    for (int64_t j = i; j < n && keys[j] == k; ++j) {
+        const int c = cost[j];
+        const bool head = count == 0 || count == per || work + c > cmax;
+        if (head && count > 0) count = work = 0;
+        flags[j] = head ? 1 : 0;
+        ++count;
+        work += c;
     }
-    const int64_t start = lo;
-    lo = i + 1;
-    hi = n;                             // one past its last index
-    while (lo < hi) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (keys[mid] <= k) lo = mid + 1; else hi = mid;
-    }
-    const int64_t run = lo - start, local = i - start;
-    const int64_t nc = (run + per - 1) / per;
-    flags[i] = (local == 0 || local * nc / run != (local - 1) * nc / run) ? 1 : 0;
 }
 
 __global__ void k_chunk_build(const uint32_t *keys, const int32_t *flags, const int32_t *cidx,
@@ -513,8 +526,10 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     e = rocprim::radix_sort_pairs(temp, temp_bytes, tk_a, tk_b, vals_a, P->tp_group,
                                   (size_t)ntp, 0, end_bit, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_chunk_flags, dim3(blocks(ntp, 256)), dim3(256), 0, s, tk_b, ntp, per,
-                       flags);
+    hipLaunchKernelGGL(k_pair_cost, dim3(blocks(ntp, 256)), dim3(256), 0, s, tk_b,
+                       P->tp_group, P->groups, cf.h, ntx, nty, ntp, vals_a);
+    hipLaunchKernelGGL(k_chunk_flags, dim3(blocks(ntp, 256)), dim3(256), 0, s, tk_b, vals_a,
+                       ntp, per, kChunkCells, flags);
     e = rocprim::exclusive_scan(temp, temp_bytes, flags, scan, (int32_t)0, (size_t)ntp,
                                 rocprim::plus<int32_t>(), s);
     if (e != hipSuccess) return e;

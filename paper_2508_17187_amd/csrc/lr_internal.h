@@ -17,6 +17,7 @@ constexpr double kCLight = 299792458.0;
 constexpr int kMaxChanPerUpload = 48;
 constexpr int kTile = 32;          // gridder tile side (cells)
 constexpr int kChunkMax = 64;      // most (tile, group) pairs per gridder workgroup
+constexpr int kChunkCells = 32 * kTile * kTile;   // most footprint cells per workgroup
 
 // ---------------------------------------------------------------------------
 // Per-channel constants formed on the host in FP64 (no contraction).
