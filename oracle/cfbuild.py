@@ -137,14 +137,24 @@ def crop_plane(K, M, O, h, t0_sq):
     return np.conj(out) / (M * M * t0_sq)
 
 
-def build_cf(grid, cf, n_nodes=64, planes=None):
+def build_cf(grid, cf, n_nodes=64, planes=None, compact=False):
     """Build the FP64 table for a synth GridSetup / CFSetup pair.  `planes`
-    (a set of (fg, k)) restricts the work to those planes; the others stay 0."""
+    (a set of (fg, k)) restricts the work to those planes; the others stay 0,
+    or with compact=True are not stored at all (offset -1), which keeps the
+    table of a large configuration small when only a few planes are needed."""
     h = half_widths(cf.n_w, cf.h_min, cf.h_max)
     M = screen_size(h, cf.screen_m)
     O = cf.oversample
     n_fg = cf.n_fg
     off, total = plane_offsets(n_fg, h, O)
+    if compact:
+        if planes is None:
+            raise ValueError("compact needs the list of planes")
+        off = np.full(n_fg * cf.n_w, -1, np.int64)
+        total = 0
+        for g, k in sorted(planes):
+            off[g * cf.n_w + k] = total
+            total += (O + 1) ** 2 * (2 * int(h[k]) + 1) ** 2
     table = np.zeros(total, np.complex128)
     psi = None
     t0 = 1.0

@@ -109,6 +109,19 @@ class Problem:
         self.ctx = c
         self.cell_l, self.cell_m = cell_l, cell_m
         self.nrow, self.nchan = c.nrow, c.nchan
+        self.partial_table = bool(np.any(self.plane_off < 0))
+
+    def _check_planes(self):
+        """With a table that holds only some planes, every kept sample must
+        use one of them (checked with this oracle's own index map)."""
+        if not self.partial_table:
+            return
+        m = self.map().reshape(-1, 8)
+        cp = np.tile(self.chan_plane, self.nrow)
+        kept = (m[:, 6] == 1) & (cp >= 0)
+        idx = m[kept, 7].astype(np.int64) * self.ocf.n_w + m[kept, 4]
+        if np.any(self.plane_off[idx] < 0):
+            raise ValueError("a kept sample needs a CF plane the table does not hold")
 
     @classmethod
     def from_workload(cls, wl, ocf, table=None, psf=False, pointing=None):
@@ -145,6 +158,7 @@ class Problem:
         return s, cnt
 
     def grid(self, vis, weight, nthreads=0, unit_vis=False, out=None):
+        self._check_planes()
         v = np.ascontiguousarray(vis, np.complex128)
         w = np.ascontiguousarray(weight, np.float64)
         g = np.zeros(self.grid_shape(), np.complex128) if out is None else out
@@ -153,6 +167,7 @@ class Problem:
         return g
 
     def degrid(self, grid, weight=None, nthreads=0):
+        self._check_planes()
         g = np.ascontiguousarray(grid, np.complex128)
         w = None if weight is None else np.ascontiguousarray(weight, np.float64)
         v = np.zeros((self.nrow, self.nchan, self.npol), np.complex128)

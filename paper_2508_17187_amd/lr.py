@@ -159,6 +159,18 @@ class CF:
                                   po.ctypes.data_as(C.c_void_p)))
         return off.value, eb.value, ne.value, po
 
+    def plane_host(self, fg, k):
+        """One (fg, k) plane of an FP64 or FP32 table as complex128 on the
+        host, flat in table order (test hook for tables too big to copy
+        whole)."""
+        off, eb, ne, po = self.layout()
+        if eb not in (8, 16):
+            raise ValueError("plane_host reads FP64 / FP32 tables")
+        i = fg * self.spec.n_w + k
+        end = int(po[i + 1]) if i + 1 < len(po) else int(ne)
+        raw = self.blob[off + eb * int(po[i]):off + eb * end].cpu().numpy()
+        return raw.view(np.complex128 if eb == 16 else np.complex64).astype(np.complex128)
+
     def table_host(self):
         """The stored table decoded to complex128 on the host (test hook):
         fp16 / bf16 entries are divided by their plane's 2^e."""
@@ -259,14 +271,19 @@ class Vis:
 class Plan:
     """Binning plan (lr_plan_build) in a device buffer owned by this object."""
 
-    def __init__(self, cf, vis, psf=False, stream=None):
+    def __init__(self, cf, vis, psf=False, stream=None, buf=None):
+        """buf: a uint8 device tensor to build into (reused when large
+        enough, e.g. by a streaming loop), else one is allocated."""
         L = lib()
         v = vis.with_(plan=None)
         d = v.desc()
         n = L.lr_plan_bytes(cf.handle, C.byref(d), int(psf))
         if n == 0:
             raise LRError(LR_E_ARG, L.lr_last_error().decode())
-        self.buf = torch.empty(n, dtype=torch.uint8, device=vis.uvw.device)
+        if buf is not None and buf.numel() >= n:
+            self.buf = buf
+        else:
+            self.buf = torch.empty(n, dtype=torch.uint8, device=vis.uvw.device)
         self.handle = C.c_void_p()
         self.cf = cf
         self.psf = bool(psf)
@@ -285,6 +302,15 @@ class Plan:
                 self.handle = C.c_void_p()
         except Exception:
             pass
+
+
+def plan_bytes(cf, vis, psf=False):
+    """Device bytes lr_plan_build needs for this vis shape."""
+    d = vis.with_(plan=None).desc()
+    n = lib().lr_plan_bytes(cf.handle, C.byref(d), int(psf))
+    if n == 0:
+        raise LRError(LR_E_ARG, lib().lr_last_error().decode())
+    return n
 
 
 def workspace_bytes(op, cf, vis, precision):

@@ -63,7 +63,7 @@ class Workload:
 
     @property
     def nsamples(self):
-        return int(self.vis.size)
+        return int(self.obs.nrow * self.obs.nchan * self.grid.npol)
 
 
 def max_abs_w_lambda(obs):
@@ -73,14 +73,16 @@ def max_abs_w_lambda(obs):
 def _build(name, *, n_ant, diameter_m, n_time, dt_s, dec_deg, freq_hz, npol,
            n_src, sigma, grid, cf, cfg_id, chan_plane=None, chan_fg=None,
            sky_half_width_deg=0.5, flux=(0.1, 1.0), log_flux=False,
-           with_vis=True, pointing_sigma=0.0, dft_device="cpu"):
+           with_vis=True, pointing_sigma=0.0, dft_device="cpu", layout_only=False):
     obs = make_observation(n_ant, diameter_m, n_time, dt_s, dec_deg, freq_hz,
                            seed=1000 + cfg_id)
     sky = random_point_sky(n_src, seed=2000 + cfg_id,
                            half_width_deg=sky_half_width_deg,
                            flux_lo=flux[0], flux_hi=flux[1], log_flux=log_flux)
     nchan = obs.nchan
-    if with_vis:
+    if layout_only:
+        v = wt = None
+    elif with_vis:
         v = dft_visibilities(obs.uvw, obs.freq_hz, sky, npol, device=dft_device)
         if sigma > 0:
             v, wt = add_noise(v, sigma, seed=3000 + cfg_id)
@@ -161,20 +163,40 @@ def config3_awproj(with_vis=True, n_time=600, nchan=64, n_fg=8, dft_device="cpu"
                   with_vis=with_vis, pointing_sigma=0.01 * fwhm, dft_device=dft_device)
 
 
-def config5_chunk(n_time=1085, nchan=64, with_vis=False):
-    """One streaming chunk of the large single image: 36 km layout, 2 s
-    dumps, 64 channels, 4 correlations; 128 w-planes with supports up to
-    129, O=20, 8192^2 x 4 at 0.3 arcsec.  1085 dumps x 351 x 64 x 4 is
-    about 1e8 samples."""
+C5_CHUNK_ROWS = 390625      # 1e8 samples per chunk at 64 channels x 4 pols
+
+
+def config5(n_time=14400, nchan=64, n_fg=8):
+    """Large single image: 351 baselines of a 36 km disc, 8 h at 2 s
+    (14,400 dumps), 64 channels over 2-4 GHz, 4 correlations
+    (1,293,926,400 samples, streamed in chunks of C5_CHUNK_ROWS rows);
+    128 w-planes with supports 17..129, O=20, Airy A-terms (25 m dishes) in
+    8 frequency groups; 8192^2 x 4 at 0.3 arcsec.  Layout only: the sample
+    values of a chunk come from chunk_values (their values do not change
+    the work)."""
     freq = channel_freqs(nchan)
+    per = nchan // n_fg
+    chan_fg = np.arange(nchan) // per
+    fg_hz = np.array([freq[chan_fg == g].mean() for g in range(n_fg)])
     grid = GridSetup(8192, 8192, 4, 1, 0.3 * ARCSEC, 0.3 * ARCSEC)
-    cf = CFSetup(terms=TERM_PS | TERM_W, oversample=20, ps_support=7, n_w=128,
-                 w_max=0.0, h_min=8, h_max=64, fg_hz=np.array([3.0e9]))
-    return _build("config5_chunk", n_ant=27, diameter_m=36000.0, n_time=n_time,
-                  dt_s=2.0, dec_deg=30.0, freq_hz=freq, npol=4, n_src=16,
-                  sigma=1e-6, grid=grid, cf=cf, cfg_id=5, with_vis=with_vis,
-                  sky_half_width_deg=20.0 / 60.0, flux=(1e-5, 1e-2),
-                  log_flux=True)
+    cf = CFSetup(terms=TERM_PS | TERM_W | TERM_A, oversample=20, ps_support=7, n_w=128,
+                 w_max=0.0, h_min=8, h_max=64, fg_hz=fg_hz, dish_m=25.0)
+    return _build("config5", n_ant=27, diameter_m=36000.0, n_time=n_time, dt_s=2.0,
+                  dec_deg=30.0, freq_hz=freq, npol=4, n_src=0, sigma=0.0, grid=grid, cf=cf,
+                  cfg_id=5, chan_fg=chan_fg, layout_only=True)
+
+
+def chunk_values(nrow, nchan, npol, seed):
+    """Seeded sample values for a chunk of rows: complex Gaussian
+    visibilities (unit variance per part) and weights uniform in [0.5, 1.5),
+    as complex64 / float32."""
+    rng = np.random.default_rng(seed)
+    shape = (nrow, nchan, npol)
+    v = np.empty(shape, np.complex64)
+    v.real = rng.standard_normal(shape, np.float32)
+    v.imag = rng.standard_normal(shape, np.float32)
+    w = (rng.random(shape, np.float32) + np.float32(0.5)).astype(np.float32)
+    return v, w
 
 
 @dataclass

@@ -1,0 +1,158 @@
+"""GPU: the large single-image configuration at its real shape.
+
+8192^2 x 4 grid at 0.3 arcsec, 128 w-planes with supports 17..129, O=20,
+Airy A-terms in 8 frequency groups (the FP32 table is ~23 GB), rows of the
+8 h, 2 s observation streamed in chunks of 390,625 rows (1e8 samples) by the
+chunk streamer.  The oracle cannot grid 1e8 samples onto this grid in test
+time, so the checks are ones it can make at any size:
+
+  * sampled CF planes against the oracle's table (compact oracle build);
+  * counters and sums of weights of two full chunks against the oracle's
+    own index map;
+  * sampled degridded visibilities against the oracle, from a seeded
+    random grid;
+  * the adjoint identity <x, G y> = <D x, W y> over the two chunks, which
+    with the sampled degrid check pins the gridder (G = D^H diag(W)).
+"""
+
+import time
+
+import numpy as np
+import pytest
+
+import synth
+import oracle
+from oracle.native import Problem
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2508_17187_amd import lr  # noqa: E402
+from paper_2508_17187_amd import workload as W  # noqa: E402
+from paper_2508_17187_amd.stream import ChunkStreamer  # noqa: E402
+
+DEV = "cuda"
+R = synth.C5_CHUNK_ROWS
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+def rel(a, b):
+    a = np.asarray(a, np.complex128).ravel()
+    b = np.asarray(b, np.complex128).ravel()
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def c5():
+    wl = synth.config5()
+    t0 = time.perf_counter()
+    cf = W.build_cf(wl, lr.LR_F32)
+    torch.cuda.synchronize()
+    say("config5 CF build %.1f s, %.1f GB" % (time.perf_counter() - t0, cf.nbytes / 1e9))
+    return wl, cf
+
+
+@pytest.fixture(scope="module")
+def two_chunks(c5):
+    """Two full chunks gridded by the streamer; the grid, sums and inputs."""
+    wl, cf = c5
+    n = 2 * R
+    vis, wt = synth.chunk_values(n, wl.obs.nchan, wl.grid.npol, seed=5005)
+    uvw_p = torch.from_numpy(np.ascontiguousarray(wl.obs.uvw[:n])).pin_memory()
+    vis_p = torch.from_numpy(vis).pin_memory()
+    wt_p = torch.from_numpy(wt).pin_memory()
+    st = ChunkStreamer(cf, lr.LR_F32, uvw_p, wl.obs.freq_hz, wl.chan_plane, wl.chan_fg,
+                       weight=wt_p, chunk_rows=R)
+    g = W.empty_grid(wl, lr.LR_F32)
+    sw = torch.zeros((1, wl.grid.npol), dtype=torch.float64, device=DEV)
+    cnt = torch.zeros(3, dtype=torch.int64, device=DEV)
+    t0 = time.perf_counter()
+    st.grid(vis_p, g, sw, cnt)
+    torch.cuda.synchronize()
+    say("config5 streamed grid of %d samples: %.2f s" % (vis.size, time.perf_counter() - t0))
+    return dict(n=n, vis=vis, wt=wt, st=st, grid=g, sumwt=sw, counters=cnt)
+
+
+def test_config5_cf_planes(c5):
+    wl, cf = c5
+    planes = [(0, 0), (3, 77), (7, 127)]
+    ocf = oracle.build_cf(wl.grid, wl.cf, planes=set(planes), compact=True)
+    for g, k in planes:
+        e = rel(cf.plane_host(g, k), ocf.plane(g, k).ravel())
+        say("plane", g, k, "rel-rms", e)
+        assert e <= 1e-6
+
+
+def test_config5_counters_and_sumwt(c5, two_chunks):
+    wl, _ = c5
+    n = two_chunks["n"]
+    dummy = oracle.build_cf(wl.grid, wl.cf, planes=set(), compact=True)
+    pr = Problem(wl.obs.uvw[:n], wl.obs.freq_hz, wl.chan_plane, wl.chan_fg, wl.grid.nx,
+                 wl.grid.ny, wl.grid.npol, wl.grid.nplane, wl.grid.cell_l, wl.grid.cell_m,
+                 dummy)
+    s_ref, c_ref = pr.sumwt(two_chunks["wt"])
+    say("counters", two_chunks["counters"].cpu().numpy(), "oracle", c_ref)
+    assert np.array_equal(two_chunks["counters"].cpu().numpy(), c_ref)
+    assert c_ref[0] > 0 and c_ref[2] > 0          # the longest baselines are dropped
+    s = two_chunks["sumwt"].cpu().numpy()
+    assert np.max(np.abs(s - s_ref) / np.abs(s_ref).max()) < 1e-12
+
+
+def test_config5_degrid_samples_and_adjoint(c5, two_chunks):
+    wl, cf = c5
+    n = two_chunks["n"]
+    shape = (wl.grid.nplane, wl.grid.npol, wl.grid.ny, wl.grid.nx)
+    gen = torch.Generator(device=DEV)
+    gen.manual_seed(5006)
+    x = torch.complex(torch.randn(shape, generator=gen, device=DEV),
+                      torch.randn(shape, generator=gen, device=DEV))
+    out = torch.empty((n, wl.obs.nchan, wl.grid.npol), dtype=torch.complex64).pin_memory()
+    t0 = time.perf_counter()
+    two_chunks["st"].degrid(x, out)
+    say("config5 streamed degrid: %.2f s" % (time.perf_counter() - t0))
+    dx = out.numpy()
+    # adjoint identity over both chunks: <x, G(W, y)> = <D x, W y>
+    g = two_chunks["grid"]
+    lhs = torch.vdot(x.flatten().to(torch.complex128), g.flatten().to(torch.complex128)).item()
+    wy = two_chunks["wt"].astype(np.float64) * two_chunks["vis"].astype(np.complex128)
+    rhs = np.vdot(dx.astype(np.complex128).ravel(), wy.ravel())
+    gap = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    say("adjoint <x, G y>", lhs, "<D x, W y>", rhs, "gap", gap)
+    assert gap < 1e-5
+    # sampled visibilities against the oracle (one channel of a few rows)
+    rng = np.random.default_rng(5007)
+    rows = np.sort(rng.choice(n, 6, replace=False))
+    dummy = oracle.build_cf(wl.grid, wl.cf, planes=set(), compact=True)
+    picks, planes = [], set()
+    for r in rows:
+        chans = rng.permutation(wl.obs.nchan)
+        for c in chans:
+            cp = np.full(wl.obs.nchan, -1, np.int32)
+            cp[c] = 0
+            pr = Problem(wl.obs.uvw[r:r + 1], wl.obs.freq_hz, cp, wl.chan_fg, wl.grid.nx,
+                         wl.grid.ny, wl.grid.npol, wl.grid.nplane, wl.grid.cell_l,
+                         wl.grid.cell_m, dummy)
+            m = pr.map()[0, c]
+            if m[6] == 1:
+                picks.append((r, c, cp))
+                planes.add((int(m[7]), int(m[4])))
+                break
+    ocf = oracle.build_cf(wl.grid, wl.cf, planes=planes, compact=True)
+    xh = x.cpu().numpy().astype(np.complex128)
+    got, ref = [], []
+    for r, c, cp in picks:
+        pr = Problem(wl.obs.uvw[r:r + 1], wl.obs.freq_hz, cp, wl.chan_fg, wl.grid.nx,
+                     wl.grid.ny, wl.grid.npol, wl.grid.nplane, wl.grid.cell_l,
+                     wl.grid.cell_m, ocf)
+        v = pr.degrid(xh, two_chunks["wt"][r:r + 1])
+        got.append(dx[r, c])
+        ref.append(v[0, c])
+    e = rel(np.array(got), np.array(ref))
+    say("sampled degrid rel-rms", e, "over", len(picks), "samples")
+    assert len(picks) >= 4 and e <= 1e-5

@@ -163,3 +163,28 @@ def test_storage_forms_round_to_nearest_even():
     # bf16 rounding: ties go to even
     assert round_bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0
     assert round_bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+
+
+def test_compact_table_holds_the_same_planes_and_guards_the_rest():
+    """A table restricted to some planes (compact storage) holds exactly the
+    full table's values for them; the oracle refuses to grid a sample whose
+    plane is missing instead of reading past the table."""
+    from oracle.native import Problem
+    wl = synth.tiny_workload(n_w=4, h_min=3, h_max=6, oversample=6, terms=TERM_PS | TERM_W,
+                             n_time=6, nchan=2)
+    full = build_cf(wl.grid, wl.cf)
+    part = build_cf(wl.grid, wl.cf, planes={(0, 1), (0, 3)}, compact=True)
+    for k in (1, 3):
+        assert np.array_equal(part.plane(0, k), full.plane(0, k))
+    assert part.table.size == full.plane(0, 1).size + full.plane(0, 3).size
+    assert part.plane_off[0] == -1 and part.plane_off[2] == -1
+    pr = Problem.from_workload(wl, part)
+    m = pr.map().reshape(-1, 8)
+    if np.any((m[:, 6] == 1) & ~np.isin(m[:, 4], [1, 3])):
+        with pytest.raises(ValueError):
+            pr.grid(wl.vis, wl.weight)
+    pr_full = Problem.from_workload(wl, build_cf(wl.grid, wl.cf, planes={(0, 0), (0, 1),
+                                                                           (0, 2), (0, 3)},
+                                                 compact=True))
+    assert np.array_equal(pr_full.grid(wl.vis, wl.weight),
+                          Problem.from_workload(wl, full).grid(wl.vis, wl.weight))
