@@ -148,6 +148,7 @@ def run_form(wl, form, steps, warmup, ev):
         "grid_call_ms": sum(og) / len(og),
         "degrid_call_ms": sum(od) / len(od),
         "cf_build_ms": 1e3 * t_cf,
+        "cf_table_bytes": int(cf.nbytes),
         "plan_build_ms": 1e3 * t_plan,
         "n_groups": info["n_groups"],
         "n_kept_pairs": info["n_kept"],
@@ -159,6 +160,13 @@ def run_form(wl, form, steps, warmup, ev):
 ELEM = {"f64": 16, "f32": 8, "f16cf": 4, "bf16cf": 4}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grid_tile_wproj2048_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2508_17187_amd", "csrc", "k_grid.hip")
+
+
+def cf_read_bytes(form, r):
+    """Kernel bytes a gridding or degridding pass must read: every group's
+    sub-kernel once, but no more than the whole table (a small table, such
+    as the Standard kernel's, is read once and then served from cache)."""
+    return min(r["taps"] * ELEM[form], r["cf_table_bytes"])
 
 
 def gridder_roofline(wl, form, r, with_traffic=True):
@@ -173,7 +181,7 @@ def gridder_roofline(wl, form, r, with_traffic=True):
     cplx = 16 if form == "f64" else 8
     flops = 8.0 * npol * r["taps"]
     grid_bytes = wl.grid.nplane * npol * wl.grid.nx * wl.grid.ny * cplx
-    bytes_ = r["n_groups"] * npol * cplx + r["taps"] * ELEM[form] + grid_bytes
+    bytes_ = r["n_groups"] * npol * cplx + cf_read_bytes(form, r) + grid_bytes
     t = r["grid_kernel_ms"] * 1e-3
     hbm = bytes_ / HBM_PEAK >= flops / PEAK[form]
     traffic = None
@@ -210,12 +218,77 @@ def gridding_roofline(wl, form, r):
     n_pairs = wl.obs.nrow * wl.obs.nchan
     grid_bytes = wl.grid.nplane * npol * wl.grid.nx * wl.grid.ny * cplx
     bytes_ = (n_pairs * npol * (cplx + real) + 4 * n_pairs + r["n_groups"] * npol * cplx
-              + r["taps"] * ELEM[form] + grid_bytes)
+              + cf_read_bytes(form, r) + grid_bytes)
     t = r["grid_call_ms"] * 1e-3
     return {"bound": "hbm", "scope": "lr_grid_overwrite call (presum + gridder)",
             "achieved": bytes_ / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": bytes_ / t / HBM_PEAK, "algorithmic_bytes_per_call": bytes_,
             "call_ms": r["grid_call_ms"]}
+
+
+def large_image_bench(steps, warmup, ev):
+    """The large single image: all 1,293,926,400 samples of the 8 h
+    observation streamed from pinned host memory in 13 chunks of 1e8
+    (copy of chunk i + 1 overlapped with planning and gridding of chunk i),
+    FP32, A+W kernels (128 planes, supports to 129, 8 frequency groups),
+    onto 8192^2 x 4.  Then one 1e8 chunk of the same layout through the
+    Standard kernel, where HBM bandwidth binds."""
+    import torch
+    import synth
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import workload as W
+    from paper_2508_17187_amd.stream import ChunkStreamer
+    p = lr.LR_F32
+    wl = synth.config5()
+    out = {"workload": "8 h at 2 s, 351 baselines, 64 channels, 4 pols = 1,293,926,400 "
+                       "visibilities in 13 chunks; A+W CF 128 planes x 8 frequency groups, "
+                       "supports 17-129, O=20; 8192x8192x4 grid at 0.3 arcsec; FP32"}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cf = W.build_cf(wl, p)
+    torch.cuda.synchronize()
+    out["cf_build_s"] = time.perf_counter() - t0
+    out["cf_gb"] = cf.nbytes / 1e9
+    n, nchan, npol = wl.obs.nrow, wl.obs.nchan, wl.grid.npol
+    # sample values drawn on the device and staged in pinned host memory
+    # (their values do not change the work)
+    uvw_p = torch.from_numpy(wl.obs.uvw).pin_memory()
+    vis_p = torch.empty((n, nchan, npol), dtype=torch.complex64).pin_memory()
+    wt_p = torch.empty((n, nchan, npol), dtype=torch.float32).pin_memory()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5008)
+    R = synth.C5_CHUNK_ROWS
+    for r0 in range(0, n, R):
+        r1 = min(n, r0 + R)
+        sh = (r1 - r0, nchan, npol)
+        vis_p[r0:r1].copy_(torch.complex(torch.randn(sh, generator=gen, device="cuda"),
+                                         torch.randn(sh, generator=gen, device="cuda")))
+        wt_p[r0:r1].copy_(torch.rand(sh, generator=gen, device="cuda") + 0.5)
+    st = ChunkStreamer(cf, p, uvw_p, wl.obs.freq_hz, wl.chan_plane, wl.chan_fg, weight=wt_p,
+                       chunk_rows=R)
+    g = W.empty_grid(wl, p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.grid(vis_p, g)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    out.update({"samples": n * nchan * npol, "chunks": len(st.chunks()),
+                "grid_s": t, "grid_vis_per_s": n * nchan * npol / t,
+                "includes": "H2D of every chunk, a plan build per chunk, presum, gridder"})
+    del st, cf, g, vis_p, wt_p, uvw_p
+    torch.cuda.empty_cache()
+    # one chunk through the Standard kernel
+    wps = synth.config5_ps()
+    vals, wts = synth.chunk_values(R, nchan, npol, seed=5009)
+    wps.obs.uvw = wps.obs.uvw[:R]
+    wps.vis, wps.weight = vals, wts
+    r, _, _ = run_form(wps, "f32", steps, warmup, ev)
+    roof = gridding_roofline(wps, "f32", r)
+    out["standard_kernel_chunk"] = {
+        "workload": "one 1e8-visibility chunk of the same layout, Standard kernel (PS, S=7, "
+                    "O=100), 8192x8192x4 grid, FP32", "result": r, "roofline": roof,
+        "roofline_gridder_kernel": gridder_roofline(wps, "f32", r, with_traffic=False)}
+    return out
 
 
 def serving_bench(n_jobs=256, rate=20.0, budget_gb=64.0, slots=4, form="f32"):
@@ -348,6 +421,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-jobs", type=int, default=256,
                     help="jobs in the serving stream (0 = skip it)")
+    ap.add_argument("--no-large", dest="large", action="store_false",
+                    help="skip the large single image (1.3e9 visibilities streamed)")
     ap.add_argument("--no-ps", dest="ps", action="store_false",
                     help="skip the Standard-kernel (HBM-bound) workload")
     ap.add_argument("--copy-calib", action="store_true",
@@ -435,9 +510,16 @@ def main():
     }
     if hbm is not None:
         out["hbm_bound_workload"] = hbm
+    if args.large:
+        log("large single image")
+        del wl
+        torch.cuda.empty_cache()
+        out["large_image"] = large_image_bench(args.steps, args.warmup, ev)
+        log("  ", json.dumps(out["large_image"]))
+        wl = None
     if args.serving_jobs > 0:
         log("serving stream of %d jobs" % args.serving_jobs)
-        del wl
+        wl = None
         torch.cuda.empty_cache()
         out["serving"] = serving_bench(args.serving_jobs, form=args.form)
         log("  ", json.dumps(out["serving"]))

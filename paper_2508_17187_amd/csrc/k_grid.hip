@@ -322,8 +322,11 @@ __global__ __launch_bounds__(256) void k_presum(
 // the track of pair c.  A wavefront covers 8 consecutive columns c x 8
 // consecutive steps m (lane = 8 * step + column), so every lane issues its
 // loads at once and 8 consecutive pairs are contiguous; a 3-step segmented
-// shuffle reduces along the steps and the last lane of each run of equal
-// groups adds it to A with one atomic.
+// shuffle reduces along the steps, and the open run of each column is
+// carried from the last step of a block to the first step of the next.
+// A finished run is added to A with an atomic, or simply stored when it is
+// a whole group: a single-run group (kSingleRun) whose run neither began
+// before this wavefront's first step nor continues past its last one.
 constexpr int kColW = 8, kColT = 8, kColBlocks = 16;
 
 template <typename T, int NPOL, bool UNIT, bool SUMS>
@@ -336,6 +339,9 @@ __global__ __launch_bounds__(256) void k_presum_col(
     const int cl = lane & (kColW - 1), tl = lane / kColW;
     const int64_t c = (wave % ncb) * kColW + cl;
     const int64_t mw = (wave / ncb) * (kColT * kColBlocks);
+    // lanes of my column, and of my column before me, in a ballot
+    const uint64_t colmask = 0x0101010101010101ull << cl;
+    const uint64_t below = colmask & ((1ull << lane) - 1);
     long long kept = 0, flagged = 0, dropped = 0;
     double sw[NPOL];
     cpx<T> carry[NPOL];
@@ -344,10 +350,18 @@ __global__ __launch_bounds__(256) void k_presum_col(
         carry[p] = {(T)0, (T)0};
     }
     int carry_g = -1, plane = -1;
-    auto add_to_A = [&](int g, const cpx<T> *v) {
+    bool carry_single = false;
+    // the run holding this wavefront's first step of my column may have
+    // begun in the previous wavefront: it is never stored, only added
+    bool open0 = false;
+    auto emit = [&](int g, bool store, const cpx<T> *v) {
         for (int p = 0; p < NPOL; ++p) {
-            atomicAdd(&A[(int64_t)g * NPOL + p].x, v[p].x);
-            if (!UNIT) atomicAdd(&A[(int64_t)g * NPOL + p].y, v[p].y);
+            if (store) {
+                A[(int64_t)g * NPOL + p] = v[p];
+            } else {
+                atomicAdd(&A[(int64_t)g * NPOL + p].x, v[p].x);
+                if (!UNIT) atomicAdd(&A[(int64_t)g * NPOL + p].y, v[p].y);
+            }
         }
     };
     // one step block in registers ahead: its loads are in flight while the
@@ -379,7 +393,8 @@ __global__ __launch_bounds__(256) void k_presum_col(
         if (b + 1 < kColBlocks) fetch(b + 1, nxt);
         cpx<T> a[NPOL];
         for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
-        const int g = cur.g;
+        const bool single = cur.g >= 0 && (cur.g & kSingleRun);
+        const int g = cur.g >= 0 ? (cur.g & ~kSingleRun) : cur.g;
         if (cur.valid) {
             // the channel, hence the plane, of a lane's column is fixed
             if (g >= 0 && plane < 0) plane = groups[g].plane;
@@ -404,8 +419,10 @@ __global__ __launch_bounds__(256) void k_presum_col(
             }
         }
         if (!SUMS) continue;
+        if (b == 0) open0 = mw > 0 && __shfl(g, cl) >= 0;
         // the first step of a column continues the run carried from the last
         // step of the previous block, or closes it
+        bool carry_ended = false;
         if (tl == 0 && carry_g >= 0) {
             if (carry_g == g) {
                 for (int p = 0; p < NPOL; ++p) {
@@ -413,9 +430,11 @@ __global__ __launch_bounds__(256) void k_presum_col(
                     a[p].y += carry[p].y;
                 }
             } else {
-                add_to_A(carry_g, carry);
+                carry_ended = true;
+                emit(carry_g, carry_single && !open0, carry);
             }
         }
+        const bool col_carry_ended = __shfl(carry_ended, cl);
         const int key = g >= 0 ? g : -1 - lane;     // lanes without a group never merge
         for (int off = kColW; off < 64; off <<= 1) {
             const int ko = __shfl_up(key, off);
@@ -429,16 +448,24 @@ __global__ __launch_bounds__(256) void k_presum_col(
             }
         }
         const int kn = __shfl_down(key, kColW);
-        if (g >= 0 && tl != kColT - 1 && kn != key) add_to_A(g, a);   // run ended in the block
+        const bool ends = g >= 0 && tl != kColT - 1 && kn != key;   // run ended in the block
+        const uint64_t endmask = __ballot(ends);
+        if (ends) {
+            const bool first = open0 && !col_carry_ended && !(endmask & below);
+            emit(g, single && !first, a);
+        }
+        if (col_carry_ended || (endmask & colmask)) open0 = false;
         // hand the last step's run to the first step of the next block
         const int src = (lane & (kColW - 1)) + (kColT - 1) * kColW;
         carry_g = __shfl(g, src);
+        carry_single = __shfl(single, src);
         for (int p = 0; p < NPOL; ++p) {
             carry[p].x = __shfl(a[p].x, src);
             carry[p].y = __shfl(a[p].y, src);
         }
     }
-    if (SUMS && tl == 0 && carry_g >= 0) add_to_A(carry_g, carry);
+    // the run still open may continue in the next wavefront
+    if (SUMS && tl == 0 && carry_g >= 0) emit(carry_g, false, carry);
     if (counters) {
         kept = wave_sum_ll(kept);
         flagged = wave_sum_ll(flagged);
@@ -838,7 +865,8 @@ __global__ __launch_bounds__(256) void k_expand(int64_t n_pairs, const int32_t *
                                                 const T *weight) {
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_pairs) return;
-    const int g = pair_group[j];
+    int g = pair_group[j];
+    if (g >= 0) g &= ~kSingleRun;
     cpx<T> out[NPOL];
     T w[NPOL];
     if (weight) vload(weight + j * NPOL, w);

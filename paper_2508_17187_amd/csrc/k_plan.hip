@@ -330,15 +330,36 @@ __global__ void k_shared_list(const int32_t *tile_state, int64_t n_tiles, int32_
     list[atomicAdd(count, 1)] = (int32_t)t;
 }
 
-// Group of every pair in natural (row, channel) order: >= 0 kept, -1
-// dropped, -2 skipped channel.
-__global__ void k_pair_group(const int32_t *order, const int32_t *gidx, int64_t n_kept,
-                             int64_t n_pairs, int32_t *pair_group) {
+// Single-run groups: with a period L, a group whose pairs are p, p + L,
+// p + 2 L, ... (one unbroken stretch of one track) is summed completely by
+// the presum lane that walks that track, which may then store the sum
+// without an atomic.  single[g] starts at 1 and is cleared by any gap.
+__global__ void k_single_init(int32_t *single, int64_t n_groups, int32_t value) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g < n_groups) single[g] = value;
+}
+
+__global__ void k_single_gaps(const int32_t *order, const int32_t *gidx, int64_t n_kept,
+                              int64_t period, int32_t *single) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 1 || i >= n_kept || gidx[i] != gidx[i - 1]) return;
+    if ((int64_t)order[i] - order[i - 1] != period) single[gidx[i]] = 0;
+}
+
+// Group of every pair in natural (row, channel) order: >= 0 kept (bit
+// kSingleRun set for a single-run group), -1 dropped, -2 skipped channel.
+__global__ void k_pair_group(const int32_t *order, const int32_t *gidx, const int32_t *single,
+                             int64_t n_kept, int64_t n_pairs, int32_t *pair_group) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_pairs) return;
     int32_t v = order[i];
     int32_t pair = v & ~(1 << 30);
-    pair_group[pair] = i < n_kept ? gidx[i] : (((v >> 30) & 1) ? -2 : -1);
+    int32_t out = ((v >> 30) & 1) ? -2 : -1;
+    if (i < n_kept) {
+        const int32_t g = gidx[i];
+        out = g | (single && single[g] ? kSingleRun : 0);
+    }
+    pair_group[pair] = out;
 }
 
 // Row period: the smallest r for which rows i and i + r have nearly the same
@@ -437,7 +458,7 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
                              const ChanConst *d_cc, const MapGeom &g, const KeyLayout &kl,
                              const CFView &cf, const int32_t *ant1, const int32_t *ant2,
                              int32_t nant, const double *ant_dlm, double du_dl,
-                             double dv_dm, int32_t per, hipStream_t s) {
+                             double dv_dm, int32_t per, int32_t cmax, hipStream_t s) {
     hipError_t e;
     int64_t n = P->n_pairs;
     uint64_t *keys_a = (uint64_t *)(buf + L.keys_a), *keys_b = (uint64_t *)(buf + L.keys_b);
@@ -481,7 +502,7 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->n_kept = (int64_t)nk;
     if (nk == 0) {
         hipLaunchKernelGGL(k_pair_group, dim3(blocks(n, 256)), dim3(256), 0, s, order, gidx,
-                           (int64_t)0, n, P->pair_group);
+                           (const int32_t *)nullptr, (int64_t)0, n, P->pair_group);
         return hipGetLastError();
     }
 
@@ -529,7 +550,7 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     hipLaunchKernelGGL(k_pair_cost, dim3(blocks(ntp, 256)), dim3(256), 0, s, tk_b,
                        P->tp_group, P->groups, cf.h, ntx, nty, ntp, vals_a);
     hipLaunchKernelGGL(k_chunk_flags, dim3(blocks(ntp, 256)), dim3(256), 0, s, tk_b, vals_a,
-                       ntp, per, kChunkCells, flags);
+                       ntp, per, cmax, flags);
     e = rocprim::exclusive_scan(temp, temp_bytes, flags, scan, (int32_t)0, (size_t)ntp,
                                 rocprim::plus<int32_t>(), s);
     if (e != hipSuccess) return e;
@@ -561,9 +582,7 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->n_chunks = nch;
     P->taps = (int64_t)taps;
 
-    // natural-order group map and the row period of the data
-    hipLaunchKernelGGL(k_pair_group, dim3(blocks(n, 256)), dim3(256), 0, s, order, gidx,
-                       (int64_t)nk, n, P->pair_group);
+    // the row period of the data, then the natural-order group map
     int32_t rmax = (int32_t)std::min<int64_t>(P->nrow - 1, 1 << 16);
     P->period = 0;
     if (rmax >= 1) {
@@ -577,6 +596,16 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
         if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
         if (r != big) P->period = (int64_t)r * P->nchan;
     }
+    // groups that are one unbroken stretch of one track (pairs of another
+    // track, or a gap, break the stride L between consecutive members)
+    int32_t *single = flags;
+    hipLaunchKernelGGL(k_single_init, dim3(blocks(ng, 256)), dim3(256), 0, s, single, ng,
+                       P->period > 0 ? 1 : 0);
+    if (P->period > 0)
+        hipLaunchKernelGGL(k_single_gaps, dim3(blocks(nk, 256)), dim3(256), 0, s, order, gidx,
+                           (int64_t)nk, P->period, single);
+    hipLaunchKernelGGL(k_pair_group, dim3(blocks(n, 256)), dim3(256), 0, s, order, gidx,
+                       (const int32_t *)single, (int64_t)nk, n, P->pair_group);
     return hipGetLastError();
 }
 

@@ -352,7 +352,7 @@ lr_status build_plan(const lr_cf *cf, const lr_vis *v, int psf, void *buf, size_
     double du_dl = 1.0 / ((double)cf->grid.nx * cf->grid.cell_l);
     double dv_dm = 1.0 / ((double)cf->grid.ny * cf->grid.cell_m);
     e = build_plan_device(P, b, L, v->uvw, d_cc, g, kl, view_of(cf), v->ant1, v->ant2,
-                          v->nant, v->ant_dlm, du_dl, dv_dm, chunk_pairs(), s);
+                          v->nant, v->ant_dlm, du_dl, dv_dm, chunk_pairs(), kChunkCells, s);
     if (e == hipErrorInvalidValue)
         return fail(LR_E_RANGE, "plan tile table overflow");
     if (e != hipSuccess) return dev_fail(e, "plan build");

@@ -18,6 +18,7 @@ constexpr int kMaxChanPerUpload = 48;
 constexpr int kTile = 32;          // gridder tile side (cells)
 constexpr int kChunkMax = 64;      // most (tile, group) pairs per gridder workgroup
 constexpr int kChunkCells = 32 * kTile * kTile;   // most footprint cells per workgroup
+constexpr int32_t kSingleRun = 1 << 30;   // pair_group flag: the group is one stretch of a track
 
 // ---------------------------------------------------------------------------
 // Per-channel constants formed on the host in FP64 (no contraction).
@@ -129,7 +130,8 @@ struct lr_plan {
     // device arrays inside the caller's buffer
     int32_t *order;            // [n_pairs] pair ids; kept (sorted) first; bit 30 set = skipped channel
     int32_t *gidx;             // [n_kept] group of each sorted kept pair
-    int32_t *pair_group;       // [n_pairs] group of each pair in natural order (-1 dropped, -2 skipped)
+    int32_t *pair_group;       // [n_pairs] group of each pair in natural order (-1 dropped,
+                               // -2 skipped; kSingleRun set for single-run groups)
     int64_t period;            // pairs between consecutive samples of one track (0: unknown)
     int32_t *group_start;      // [n_groups + 1]
     lr::GroupMeta *groups;     // [n_groups]

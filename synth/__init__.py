@@ -17,5 +17,5 @@ from .sky import PointSky, random_point_sky, dft_visibilities, add_noise  # noqa
 from .configs import (  # noqa: F401
     GridSetup, CFSetup, Workload,
     config1_plain, config2_wproj, config2_ps, config3_awproj, config4_jobs,
-    config5, chunk_values, C5_CHUNK_ROWS, tiny_workload,
+    config5, config5_ps, chunk_values, C5_CHUNK_ROWS, tiny_workload,
 )

@@ -186,6 +186,17 @@ def config5(n_time=14400, nchan=64, n_fg=8):
                   cfg_id=5, chan_fg=chan_fg, layout_only=True)
 
 
+def config5_ps(n_time=14400, nchan=64):
+    """The large-image layout gridded with the Standard kernel (PS only,
+    S=7, O=100, one plane): the shape on which HBM bandwidth binds."""
+    w = config5(n_time=n_time, nchan=nchan)
+    w.name = "config5_ps"
+    w.chan_fg = np.zeros(nchan, np.int32)
+    w.cf = CFSetup(terms=TERM_PS, oversample=100, ps_support=7, n_w=1, w_max=0.0,
+                   h_min=3, h_max=3, fg_hz=np.array([3.0e9]))
+    return w
+
+
 def chunk_values(nrow, nchan, npol, seed):
     """Seeded sample values for a chunk of rows: complex Gaussian
     visibilities (unit variance per part) and weights uniform in [0.5, 1.5),

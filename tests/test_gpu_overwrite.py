@@ -36,8 +36,8 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def dense_workload(pointing=0.0, seed_id=93):
-    wl = synth.tiny_workload(n_w=6, h_min=3, h_max=7, oversample=8,
+def dense_workload(pointing=0.0, seed_id=93, h_max=7):
+    wl = synth.tiny_workload(n_w=6, h_min=3, h_max=h_max, oversample=8,
                              terms=TERM_PS | TERM_W | TERM_A, nchan=4, n_time=64, nx=112,
                              ny=72, cell_arcsec=3.0, diameter_m=6000.0, nplane=2,
                              chan_plane=[0, 1, -1, 0], chan_fg=[0, 0, 1, 1],
@@ -47,9 +47,10 @@ def dense_workload(pointing=0.0, seed_id=93):
     return wl
 
 
-@pytest.fixture(scope="module")
-def dense():
-    wl = dense_workload()
+# widest support 15 and 19
+@pytest.fixture(scope="module", params=[7, 9], ids=["S15", "S19"])
+def dense(request):
+    wl = dense_workload(h_max=request.param)
     return wl, oracle.build_cf(wl.grid, wl.cf)
 
 
@@ -139,8 +140,9 @@ def test_overwrite_empty_input_clears(dense):
         assert cnt[1].item() == wl.weight.size
 
 
-def test_overwrite_pointing_phasor():
-    wl = dense_workload(pointing=3e-5, seed_id=94)
+@pytest.mark.parametrize("h_max", [7, 9], ids=["S15", "S19"])
+def test_overwrite_pointing_phasor(h_max):
+    wl = dense_workload(pointing=3e-5, seed_id=94, h_max=h_max)
     ocf = oracle.build_cf(wl.grid, wl.cf)
     p = lr.LR_F32
     cf = W.build_cf(wl, p)
@@ -150,3 +152,45 @@ def test_overwrite_pointing_phasor():
     torch.cuda.synchronize()
     pr = Problem.from_workload(wl, ocf)
     assert rel(g.cpu().numpy(), pr.grid(wl.vis, wl.weight)) <= TOL["f32"]
+
+
+def test_standard_kernel_tiles_shared_by_many_chunks():
+    """Standard kernel (S = 7) on a 64 x 64 grid whose tiles hold over 1024
+    (tile, group) pairs, so each is cut into many chunks that add atomically:
+    grid, overwrite and PSF against the oracle."""
+    wl = synth.tiny_workload(n_ant=12, n_time=300, dt_s=60.0, nchan=4, nx=64, ny=64,
+                             cell_arcsec=30.0, diameter_m=3000.0, oversample=16,
+                             terms=TERM_PS, h_min=3, h_max=3, cfg_id=95)
+    ocf = oracle.build_cf(wl.grid, wl.cf)
+    pr = Problem.from_workload(wl, ocf)
+    m = pr.map().reshape(-1, 8)
+    k = m[m[:, 6] == 1]
+    groups = np.unique(np.stack([k[:, 4], k[:, 5], k[:, 1], k[:, 0], k[:, 3], k[:, 2]], 1),
+                       axis=0)
+    per_tile = {}
+    for pv, pu in groups[:, 2:4]:
+        for ty in range((pv - 3) // 32, (pv + 3) // 32 + 1):
+            for tx in range((pu - 3) // 32, (pu + 3) // 32 + 1):
+                per_tile[(ty, tx)] = per_tile.get((ty, tx), 0) + 1
+    assert max(per_tile.values()) > 1024          # the case this test is for
+    ref = pr.grid(wl.vis, wl.weight)
+    for form in ("f64", "f32"):
+        p = PREC[form]
+        cf = W.build_cf(wl, p)
+        v = W.device_vis(wl, p)
+        v.plan = lr.Plan(cf, v)
+        g = W.empty_grid(wl, p)
+        lr.lr_grid(cf, v, p, g)
+        g2, sw, cnt = garbage_outputs(wl, p)
+        lr.lr_grid_overwrite(cf, v, p, g2, sumwt=sw, counters=cnt)
+        torch.cuda.synchronize()
+        assert rel(g.cpu().numpy(), ref) <= TOL[form]
+        assert rel(g2.cpu().numpy(), ref) <= TOL[form]
+    psf_ref, _, _ = pr.psf(wl.weight)
+    p = lr.LR_F64
+    cf = W.build_cf(wl, p)
+    v = W.device_vis(wl, p)
+    g = W.empty_grid(wl, p)
+    lr.lr_make_psf(cf, v, p, g)
+    torch.cuda.synchronize()
+    assert rel(g.cpu().numpy(), psf_ref) <= TOL["f64"]

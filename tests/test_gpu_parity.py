@@ -39,8 +39,8 @@ def say(*a):
     print(*a, flush=True)
 
 
-def awp_workload(nx=128, ny=96, pointing=0.0, seed_id=91):
-    wl = synth.tiny_workload(n_w=6, h_min=3, h_max=7, oversample=8,
+def awp_workload(nx=128, ny=96, pointing=0.0, seed_id=91, h_max=7):
+    wl = synth.tiny_workload(n_w=6, h_min=3, h_max=h_max, oversample=8,
                              terms=TERM_PS | TERM_W | TERM_A, nchan=4, n_time=16, nx=nx,
                              ny=ny, cell_arcsec=6.0, diameter_m=6000.0, nplane=2,
                              chan_plane=[0, 1, -1, 0], chan_fg=[0, 0, 1, 1],
@@ -50,15 +50,20 @@ def awp_workload(nx=128, ny=96, pointing=0.0, seed_id=91):
     return wl
 
 
-@pytest.fixture(scope="module")
-def awp():
-    wl = awp_workload()
+# widest support 15 (within one 32-cell tile plus a band) and 19
+KERNELS = [7, 9]
+KERNEL_IDS = ["S15", "S19"]
+
+
+@pytest.fixture(scope="module", params=KERNELS, ids=KERNEL_IDS)
+def awp(request):
+    wl = awp_workload(h_max=request.param)
     return wl, oracle.build_cf(wl.grid, wl.cf)
 
 
-@pytest.fixture(scope="module")
-def awp_po():
-    wl = awp_workload(pointing=3e-5, seed_id=92)
+@pytest.fixture(scope="module", params=KERNELS, ids=KERNEL_IDS)
+def awp_po(request):
+    wl = awp_workload(pointing=3e-5, seed_id=92, h_max=request.param)
     return wl, oracle.build_cf(wl.grid, wl.cf)
 
 
@@ -354,3 +359,29 @@ def test_errors_leave_outputs_untouched(awp):
         lr.lr_grid(cf, v, lr.LR_F64, g)       # storage f32 vs precision f64
     assert ei.value.status == lr.LR_E_DTYPE
     assert g.abs().sum().item() == 0
+
+
+@pytest.mark.parametrize("dt_s", [0.5, 20.0])
+def test_tracks_longer_than_one_wavefront(dt_s):
+    """Time-major rows with 400 dumps: the track presum cuts each track into
+    several wavefront segments, so group runs cross segment boundaries (they
+    are added atomically) or lie inside one (a single-run group is stored).
+    Short dumps give long runs, long dumps mostly one-sample groups."""
+    wl = synth.tiny_workload(n_ant=5, n_time=400, dt_s=dt_s, nchan=2, nx=96, ny=96,
+                             cell_arcsec=4.0, diameter_m=3000.0, n_w=4, h_min=3, h_max=5,
+                             oversample=8, terms=TERM_PS | TERM_W, cfg_id=96)
+    ocf = oracle.build_cf(wl.grid, wl.cf)
+    pr = Problem.from_workload(wl, ocf)
+    ref = pr.grid(wl.vis, wl.weight)
+    s_ref, c_ref = pr.sumwt(wl.weight)
+    for form in ("f64", "f32"):
+        g, sw, cnt = run_grid(wl, form, plan=True)
+        say("long tracks", dt_s, form, rel(g, ref))
+        assert rel(g, ref) <= TOL[form]
+        assert np.array_equal(cnt, c_ref)
+        assert np.max(np.abs(sw - s_ref) / np.abs(s_ref).max()) < 1e-12
+    p = lr.LR_F64
+    cf = W.build_cf(wl, p)
+    v = W.device_vis(wl, p)
+    v.plan = lr.Plan(cf, v)
+    assert v.plan.info()["n_groups"] < v.plan.info()["n_kept"] or dt_s > 1
