@@ -601,14 +601,14 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     for (int t = threadIdx.x; t < n; t += blockDim.x) {
         const int32_t g = a.tp_group[s0 + t];
         const GroupMeta gm = a.groups[g];
-        const int h = a.cf.h[gm.k];
+        const int h = gm.h;
         TileItem ti;
         ti.cf_off = gm.cf_off;
         ti.bx = gm.pu - h;
         ti.by = gm.pv - h;
         ti.S = 2 * h + 1;
         ti.conj = gm.conj;
-        ti.sc = a.cf.scale[gm.fg * a.cf.n_w + gm.k];
+        ti.sc = gm.sc;
         ti.h = h;
         items[t] = ti;
         for (int p = 0; p < NPOL; ++p) avs[t * NPOL + p] = Av[(int64_t)g * NPOL + p];
@@ -792,11 +792,10 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
     const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + uni(threadIdx.x >> 6);
     if (g >= a.n_groups) return;
     const GroupMeta gm = a.groups[g];
-    const int k = uni(gm.k);
-    const int h = uni(a.cf.h[k]);
+    const int h = uni(gm.h);
     const int S = 2 * h + 1;
     const int SS = S * S;
-    const float sc = a.cf.scale[uni(gm.fg) * a.cf.n_w + k];
+    const float sc = gm.sc;
     const bool cj = uni(gm.conj) != 0;
     const char *cfb = (const char *)a.cf.table + uni64(gm.cf_off) * E;
     // corner cell (tap (0, 0)) of pol 0
@@ -854,6 +853,68 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
     for (int p = 0; p < NPOL; ++p) {
         T x = wave_sum(sum[p].x), y = wave_sum(sum[p].y);
         if (lane == 0) out[g * NPOL + p] = {x, y};
+    }
+}
+
+// Small supports (S <= 2 kDegridSmallH + 1): a 7 x 7 footprint would leave
+// most of a wavefront idle, so 16 lanes take one group (four groups per
+// wavefront), four taps per lane in flight, and reduce over their 16 lanes.
+constexpr int kDegridSmallH = 7;
+
+template <typename T, int ST, int NPOL, bool PO>
+__global__ __launch_bounds__(256) void k_degrid_small(DegridArgs a) {
+    constexpr int E = CFRaw<ST>::bytes;
+    typedef typename CFRaw<ST>::R Raw;
+    const int sub = threadIdx.x & 15;
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
+    const bool live = g < a.n_groups;
+    cpx<T> sum[NPOL];
+    for (int p = 0; p < NPOL; ++p) sum[p] = {(T)0, (T)0};
+    if (live) {
+        const GroupMeta gm = a.groups[g];
+        const int h = gm.h;
+        const int S = 2 * h + 1;
+        const int SS = S * S;
+        const float invS = 1.0f / (float)S;
+        const char *cfb = (const char *)a.cf.table + gm.cf_off * E;
+        const int64_t corner = gm.cell - (int64_t)h * a.nx - h;
+        const T *grid = (const T *)a.grid;
+        for (int t0 = 0; t0 < SS; t0 += 64) {
+            Raw cr[4];
+            cpx<T> gv[4][NPOL];
+            int tys[4], txs[4];
+            for (int u = 0; u < 4; ++u) {
+                const int tap = t0 + u * 16 + sub;
+                int ty, tx;
+                divmod_small(tap, S, invS, ty, tx);
+                tys[u] = ty;
+                txs[u] = tx;
+                if (tap < SS) {
+                    cr[u] = *(const Raw *)(cfb + (int64_t)tap * E);
+                    const int64_t cell = corner + (int64_t)ty * a.nx + tx;
+                    for (int p = 0; p < NPOL; ++p) {
+                        const T *q = grid + 2 * (cell + p * a.pol_stride);
+                        gv[u][p] = {q[0], q[1]};
+                    }
+                }
+            }
+            for (int u = 0; u < 4; ++u) {
+                if (t0 + u * 16 + sub >= SS) continue;
+                cpx<T> cv = CFRaw<ST>::decode(cr[u], gm.sc);
+                if (gm.conj) cv.y = -cv.y;
+                if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
+                for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
+            }
+        }
+    }
+    for (int p = 0; p < NPOL; ++p)
+        for (int off = 8; off > 0; off >>= 1) {
+            sum[p].x += __shfl_xor(sum[p].x, off);
+            sum[p].y += __shfl_xor(sum[p].y, off);
+        }
+    if (live && sub == 0) {
+        cpx<T> *out = (cpx<T> *)a.Vg;
+        for (int p = 0; p < NPOL; ++p) out[g * NPOL + p] = sum[p];
     }
 }
 
@@ -1026,32 +1087,42 @@ hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *
 }
 
 template <typename T, int ST, int NPOL>
-static hipError_t degrid_t(const DegridArgs &da, bool po, hipStream_t s) {
-    dim3 grd(nblk(da.n_groups, 4)), blk(256);
+static hipError_t degrid_t(const DegridArgs &da, bool po, bool small, hipStream_t s) {
+    dim3 blk(256);
+    if (small) {
+        dim3 grd(nblk(da.n_groups, 16));
+        if (po) hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, true>), grd, blk, 0, s, da);
+        else hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, false>), grd, blk, 0, s, da);
+        return hipGetLastError();
+    }
+    dim3 grd(nblk(da.n_groups, 4));
     if (po) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, true>), grd, blk, 0, s, da);
     else hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false>), grd, blk, 0, s, da);
     return hipGetLastError();
 }
 
 template <typename T, int ST>
-static hipError_t degrid_np(const DegridArgs &da, int npol, bool po, hipStream_t s) {
+static hipError_t degrid_np(const DegridArgs &da, int npol, bool po, bool small,
+                            hipStream_t s) {
     switch (npol) {
-        case 1: return degrid_t<T, ST, 1>(da, po, s);
-        case 2: return degrid_t<T, ST, 2>(da, po, s);
-        default: return degrid_t<T, ST, 4>(da, po, s);
+        case 1: return degrid_t<T, ST, 1>(da, po, small, s);
+        case 2: return degrid_t<T, ST, 2>(da, po, small, s);
+        default: return degrid_t<T, ST, 4>(da, po, small, s);
     }
 }
 
 hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
-                         int precision, int32_t npol, int32_t nx, int32_t ny, hipStream_t s) {
+                         int precision, int32_t npol, int32_t nx, int32_t ny, int32_t h_max,
+                         hipStream_t s) {
     if (P->n_groups == 0) return hipSuccess;
     DegridArgs da{P->groups, P->n_groups, grid, Vg, cf, nx, ny, (int64_t)nx * ny};
     bool po = P->po != 0;
+    bool sm = h_max <= kDegridSmallH;
     switch (precision) {
-        case LR_F64: return degrid_np<double, LR_F64>(da, npol, po, s);
-        case LR_F32: return degrid_np<float, LR_F32>(da, npol, po, s);
-        case LR_F32_CF16: return degrid_np<float, LR_F32_CF16>(da, npol, po, s);
-        default: return degrid_np<float, LR_F32_CFBF16>(da, npol, po, s);
+        case LR_F64: return degrid_np<double, LR_F64>(da, npol, po, sm, s);
+        case LR_F32: return degrid_np<float, LR_F32>(da, npol, po, sm, s);
+        case LR_F32_CF16: return degrid_np<float, LR_F32_CF16>(da, npol, po, sm, s);
+        default: return degrid_np<float, LR_F32_CFBF16>(da, npol, po, sm, s);
     }
 }
 

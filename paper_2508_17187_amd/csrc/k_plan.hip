@@ -182,6 +182,8 @@ __global__ void k_group_meta(const int32_t *vals, const int32_t *flags, const in
     gm.ov = m.ov;
     gm.plane = ch.plane;
     gm.fg = ch.fg;
+    gm.h = h;
+    gm.sc = cf.scale[(int64_t)ch.fg * g.n_w + m.k];
     gm.f = 1.0;
     gm.bu = 0.0;
     gm.bv = 0.0;

@@ -622,7 +622,7 @@ lr_status lr_degrid(const lr_cf *cf, lr_vis *vis, lr_precision precision, const 
     ProfileScope prof(s);
     prof.begin();
     hipError_t e = launch_degrid(P, view_of(cf), grid, Vg, precision, vis->npol, cf->grid.nx,
-                                 cf->grid.ny, s);
+                                 cf->grid.ny, h_max_of(cf), s);
     prof.end();
     if (e == hipSuccess) e = launch_expand(P, Vg, vis->vis, vis->weight, precision, vis->npol, s);
     if (e == hipSuccess && counters)

@@ -83,6 +83,8 @@ struct GroupMeta {
     int32_t k, conj;        // w-plane, conjugate flag
     int32_t ou, ov;         // oversampling offsets in [-O/2, O/2)
     int32_t plane, fg;
+    int32_t h;              // half-width of the w-plane's support
+    float sc;               // 2^-e of the CF plane (1 for f32 / f64 storage)
     double f;               // pointing loss factor (1 without phasor)
     double bu, bv;          // phasor slopes du*dl/O and dv*dm/O (0 without)
 };

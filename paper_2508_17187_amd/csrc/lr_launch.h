@@ -74,8 +74,11 @@ hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *
                              size_t sumwt_bytes, int64_t *counters, void *grid,
                              int precision, int32_t npol, int32_t nx, int32_t ny, bool set,
                              hipStream_t s);
+// h_max: widest half-width of the table (small supports take the
+// four-groups-per-wavefront degridder)
 hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
-                         int precision, int32_t npol, int32_t nx, int32_t ny, hipStream_t s);
+                         int precision, int32_t npol, int32_t nx, int32_t ny, int32_t h_max,
+                         hipStream_t s);
 hipError_t launch_expand(const lr_plan *P, const void *Vg, void *vis, const void *weight,
                          int precision, int32_t npol, hipStream_t s);
 
