@@ -291,6 +291,46 @@ def large_image_bench(steps, warmup, ev):
     return out
 
 
+def image_bench(wl, form, steps, ev):
+    """Residual image of the W-projection data against a 20-component model
+    (Eq. ResIm): predict (F, degrid), subtract, grid, F^dagger (rocFFT) and
+    normalise by the grid correction of the w = 0 plane and the sums of
+    weights."""
+    import torch
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import workload as W
+    from paper_2508_17187_amd.imaging import dirty_image, grid_correction, residual_image
+    p = lr.PRECISIONS[form]
+    cf = W.build_cf(wl, p)
+    v = W.device_vis(wl, p)
+    v.plan = lr.Plan(cf, v)
+    g = wl.grid
+    rdt = torch.float64 if p == lr.LR_F64 else torch.float32
+    model = torch.zeros((g.nplane, g.npol, g.ny, g.nx), dtype=rdt, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(2100)
+    iy = torch.randint(g.ny // 4, 3 * g.ny // 4, (20,), generator=gen, device="cuda")
+    ix = torch.randint(g.nx // 4, 3 * g.nx // 4, (20,), generator=gen, device="cuda")
+    model[:, :, iy, ix] = 0.5
+    gcf = grid_correction(cf)
+    out = {}
+    for name, fn in (("dirty_image_ms", lambda: dirty_image(cf, v, p, gcf=gcf)),
+                     ("residual_image_ms", lambda: residual_image(cf, v, p, model, gcf=gcf))):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        out[name] = a.elapsed_time(b) / steps
+    img, _ = dirty_image(cf, v, p, gcf=gcf)
+    out["dirty_peak_jy"] = float(img[0, 0].max().item())
+    out["form"] = form
+    return out
+
+
 def serving_bench(n_jobs=256, rate=20.0, budget_gb=64.0, slots=4, form="f32"):
     """Poisson stream of grid / degrid jobs (configuration 4): visibility
     counts log-uniform in [1e4, 2e7] (4 pols, one 3 GHz channel), grids of
@@ -467,6 +507,9 @@ def main():
         for f in forms:
             res[f]["speedup_vs_f64"] = res[f]["vis_per_s"] / res["f64"]["vis_per_s"]
     del grids
+    log("residual image")
+    images = image_bench(wl, args.form, args.steps, ev)
+    log("  ", json.dumps(images))
     hbm = None
     if args.ps:
         # the same data through the Standard kernel (PS, S = 7, O = 100, one
@@ -508,6 +551,7 @@ def main():
         "roofline": roof,
         "forms": res,
     }
+    out["image"] = images
     if hbm is not None:
         out["hbm_bound_workload"] = hbm
     if args.large:

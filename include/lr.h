@@ -245,6 +245,27 @@ lr_status lr_sumwt(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
                    double *sumwt, int64_t *counters, void *work, size_t work_bytes,
                    lr_stream stream);
 
+/* ---- image plane around the hot path (residual image, Eq. ResIm) ---------- */
+
+/* Grid correction of plane (fg, k), which must be separable (PS only, or the
+ * w = 0 plane of a PS + W table): C[o_v][o_u][t_v][t_u] = c1[o_v][t_v]
+ * c1[o_u][t_u], with c1 the o_v = 0, t_v = 0 row over sqrt(C(0, 0)).  out
+ * (device, complex128 [n]) = (1/O) sum over o in [-O/2, O/2) and t of
+ * c1[o][t] exp(2 pi i (t - o/O) xi), xi = (i - n/2)/n: the mean image-plane
+ * response of one sample.  LR_E_ARG for a plane with an A or W (k > 0)
+ * term, LR_E_RANGE for (fg, k) outside the table. */
+lr_status lr_gcf(const lr_cf *cf, int32_t fg, int32_t k, int32_t n, void *out,
+                 lr_stream stream);
+
+/* out[P][pol][iy][ix] = Re(img[P][pol][iy][ix]) / (gcf_x[ix] gcf_y[iy]
+ * sumwt[P][pol]): the normalisation of F^dagger(grid) (computed by the
+ * caller, e.g. with rocFFT) into an image.  img is complex128 (LR_F64) or
+ * complex64 (other forms), out float64 or float32 of the grid's shape;
+ * gcf_x [nx], gcf_y [ny], sumwt [nplane][npol] are FP64; all device. */
+lr_status lr_image_normalize(const lr_cf *cf, lr_precision precision, const void *img,
+                             const double *gcf_x, const double *gcf_y, const double *sumwt,
+                             void *out, lr_stream stream);
+
 /* Test hook: the index map of every (row, channel) as int32
  * out[nrow][nchan][8] = {p_u, p_v, o_u, o_v, k, conj, keep, fg} (device). */
 lr_status lr_debug_map(const lr_cf *cf, const lr_vis *vis, int psf, int32_t *out,

@@ -521,6 +521,44 @@ lr_status lr_plan_build(const lr_cf *cf, const lr_vis *vis, int psf, void *buf, 
 
 void lr_plan_free(lr_plan *plan) { delete plan; }
 
+lr_status lr_gcf(const lr_cf *cf, int32_t fg, int32_t k, int32_t n, void *out,
+                 lr_stream stream) {
+    if (!cf || !out) return fail(LR_E_ARG, "NULL argument");
+    if (n <= 0) return fail(LR_E_ARG, "n must be positive");
+    if (fg < 0 || fg >= cf->spec.n_fg || k < 0 || k >= cf->spec.n_w)
+        return fail(LR_E_RANGE, "plane (%d, %d) out of range", fg, k);
+    if (cf->spec.terms & LR_TERM_A)
+        return fail(LR_E_ARG, "grid correction needs a separable plane (no A term)");
+    if ((cf->spec.terms & LR_TERM_W) && k != 0 && cf->spec.n_w > 1)
+        return fail(LR_E_ARG, "grid correction needs a separable plane (w-plane 0)");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t i = (size_t)fg * cf->spec.n_w + k;
+    float sc = 1.0f;
+    if (cf->elem_bytes == 4) {
+        int32_t e = 0;
+        hipError_t he = hipMemcpyAsync(&e, cf->d_exp + i, sizeof e, hipMemcpyDeviceToHost, s);
+        if (he == hipSuccess) he = hipStreamSynchronize(s);
+        if (he != hipSuccess) return dev_fail(he, "read plane exponent");
+        sc = std::ldexp(1.0f, -e);
+    }
+    hipError_t e = launch_gcf(view_of(cf), cf->plane_off[i], cf->h[k], sc, n, (double2 *)out, s);
+    if (e != hipSuccess) return dev_fail(e, "gcf");
+    return LR_OK;
+}
+
+lr_status lr_image_normalize(const lr_cf *cf, lr_precision precision, const void *img,
+                             const double *gcf_x, const double *gcf_y, const double *sumwt,
+                             void *out, lr_stream stream) {
+    if (!cf || !img || !gcf_x || !gcf_y || !sumwt || !out) return fail(LR_E_ARG, "NULL argument");
+    if (precision < LR_F64 || precision > LR_F32_CFBF16) return fail(LR_E_DTYPE, "bad precision");
+    const lr_grid_spec &g = cf->grid;
+    hipError_t e = launch_normalize(img, gcf_x, gcf_y, sumwt, g.nx, g.ny,
+                                    (int64_t)g.nplane * g.npol, precision, out,
+                                    (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "image normalisation");
+    return LR_OK;
+}
+
 lr_status lr_plan_info(const lr_plan *plan, int64_t *n_groups, int64_t *n_kept,
                        int64_t *n_pairs, int64_t *taps) {
     if (!plan) return fail(LR_E_ARG, "plan is NULL");

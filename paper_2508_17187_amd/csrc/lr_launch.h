@@ -82,4 +82,11 @@ hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, v
 hipError_t launch_expand(const lr_plan *P, const void *Vg, void *vis, const void *weight,
                          int precision, int32_t npol, hipStream_t s);
 
+// ---- image plane (k_image.hip) ------------------------------------------------
+hipError_t launch_gcf(const CFView &cf, int64_t plane_base, int32_t h, float sc, int32_t n,
+                      double2 *out, hipStream_t s);
+hipError_t launch_normalize(const void *img, const double *gx, const double *gy,
+                            const double *sumwt, int32_t nx, int32_t ny, int64_t n_planes,
+                            int precision, void *out, hipStream_t s);
+
 }  // namespace lr

@@ -81,6 +81,9 @@ EXPORTS = {
     "lr_sumwt": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                            C.c_size_t, C.c_void_p]),
     "lr_debug_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
+    "lr_gcf": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "lr_image_normalize": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
+                                     C.c_void_p, C.c_void_p, C.c_void_p]),
     "lr_status_str": (C.c_char_p, [C.c_int]),
     "lr_last_error": (C.c_char_p, []),
 }
@@ -387,3 +390,20 @@ def lr_cf_build(grid, spec, device="cuda", stream=None):
 
 def lr_plan_build(cf, vis, psf=False, stream=None):
     return Plan(cf, vis, psf=psf, stream=stream)
+
+
+def lr_gcf(cf, n, fg=0, k=0, device="cuda", stream=None):
+    """Grid correction of a separable plane: complex128 [n] on the device."""
+    out = torch.empty(n, dtype=torch.complex128, device=device)
+    _check(lib().lr_gcf(cf.handle, fg, k, n, _ptr(out), _stream(stream)))
+    return out
+
+
+def lr_image_normalize(cf, precision, img, gcf_x, gcf_y, sumwt, out=None, stream=None):
+    """Re(img) / (gcf_x gcf_y sumwt) for img [nplane, npol, ny, nx]."""
+    if out is None:
+        out = torch.empty(img.shape, dtype=torch.float64 if precision == LR_F64
+                          else torch.float32, device=img.device)
+    _check(lib().lr_image_normalize(cf.handle, precision, _ptr(img), _ptr(gcf_x), _ptr(gcf_y),
+                                    _ptr(sumwt), _ptr(out), _stream(stream)))
+    return out
