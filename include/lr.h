@@ -266,6 +266,23 @@ lr_status lr_image_normalize(const lr_cf *cf, lr_precision precision, const void
                              const double *gcf_x, const double *gcf_y, const double *sumwt,
                              void *out, lr_stream stream);
 
+/* ---- minor cycle (ModelUpdate of the imaging section) -------------------- */
+
+/* Hogbom minor cycle on one image plane [ny][nx] (float64 with LR_F64,
+ * float32 with LR_F32; all device): repeatedly take the pixel of largest
+ * |residual| (lowest row-major index on ties); stop when it is below
+ * `threshold` or `niter` subtractions are done; otherwise add gain x peak
+ * to model at that pixel and subtract gain x peak x psf from the
+ * overlapping part of residual, with the psf's centre (ny/2, nx/2) on the
+ * peak.  residual is updated in place, model accumulated.  *iterations
+ * (host) receives the number of subtractions; the call synchronises the
+ * stream to read it.  work: device scratch of lr_hogbom_work_bytes bytes.
+ * LR_E_ARG for gain outside (0, 1] or niter < 0. */
+size_t lr_hogbom_work_bytes(int32_t nx, int32_t ny);
+lr_status lr_hogbom(const void *psf, void *residual, void *model, int32_t nx, int32_t ny,
+                    lr_precision precision, double gain, double threshold, int32_t niter,
+                    int32_t *iterations, void *work, size_t work_bytes, lr_stream stream);
+
 /* Test hook: the index map of every (row, channel) as int32
  * out[nrow][nchan][8] = {p_u, p_v, o_u, o_v, k, conj, keep, fg} (device). */
 lr_status lr_debug_map(const lr_cf *cf, const lr_vis *vis, int psf, int32_t *out,

@@ -559,6 +559,30 @@ lr_status lr_image_normalize(const lr_cf *cf, lr_precision precision, const void
     return LR_OK;
 }
 
+size_t lr_hogbom_work_bytes(int32_t nx, int32_t ny) {
+    if (nx <= 0 || ny <= 0) { fail(LR_E_ARG, "image size must be positive"); return 0; }
+    return hogbom_work_bytes(nx, ny);
+}
+
+lr_status lr_hogbom(const void *psf, void *residual, void *model, int32_t nx, int32_t ny,
+                    lr_precision precision, double gain, double threshold, int32_t niter,
+                    int32_t *iterations, void *work, size_t work_bytes, lr_stream stream) {
+    if (!psf || !residual || !model || !iterations || !work)
+        return fail(LR_E_ARG, "NULL argument");
+    if (nx <= 0 || ny <= 0) return fail(LR_E_ARG, "image size must be positive");
+    if (precision != LR_F64 && precision != LR_F32)
+        return fail(LR_E_DTYPE, "images are float64 (LR_F64) or float32 (LR_F32)");
+    if (!(gain > 0.0 && gain <= 1.0)) return fail(LR_E_ARG, "gain must be in (0, 1]");
+    if (niter < 0) return fail(LR_E_ARG, "niter must be >= 0");
+    if (work_bytes < hogbom_work_bytes(nx, ny))
+        return fail(LR_E_WORKSPACE, "workspace needs %zu bytes, got %zu",
+                    hogbom_work_bytes(nx, ny), work_bytes);
+    hipError_t e = launch_hogbom(residual, psf, model, nx, ny, precision, gain, threshold,
+                                 niter, work, iterations, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "hogbom");
+    return LR_OK;
+}
+
 lr_status lr_plan_info(const lr_plan *plan, int64_t *n_groups, int64_t *n_kept,
                        int64_t *n_pairs, int64_t *taps) {
     if (!plan) return fail(LR_E_ARG, "plan is NULL");

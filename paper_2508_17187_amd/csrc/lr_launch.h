@@ -89,4 +89,11 @@ hipError_t launch_normalize(const void *img, const double *gx, const double *gy,
                             const double *sumwt, int32_t nx, int32_t ny, int64_t n_planes,
                             int precision, void *out, hipStream_t s);
 
+// ---- minor cycle (k_hogbom.hip) -------------------------------------------------
+constexpr int kHogbomBlocks = 1024;      // workgroups of the peak search
+size_t hogbom_work_bytes(int32_t nx, int32_t ny);
+hipError_t launch_hogbom(void *res, const void *psf, void *model, int32_t nx, int32_t ny,
+                         int precision, double gain, double threshold, int32_t niter,
+                         void *work, int32_t *iters, hipStream_t s);
+
 }  // namespace lr

@@ -82,6 +82,10 @@ EXPORTS = {
                            C.c_size_t, C.c_void_p]),
     "lr_debug_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "lr_gcf": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "lr_hogbom_work_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "lr_hogbom": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int,
+                            C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
+                            C.c_size_t, C.c_void_p]),
     "lr_image_normalize": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p]),
     "lr_status_str": (C.c_char_p, [C.c_int]),
@@ -407,3 +411,17 @@ def lr_image_normalize(cf, precision, img, gcf_x, gcf_y, sumwt, out=None, stream
     _check(lib().lr_image_normalize(cf.handle, precision, _ptr(img), _ptr(gcf_x), _ptr(gcf_y),
                                     _ptr(sumwt), _ptr(out), _stream(stream)))
     return out
+
+
+def lr_hogbom(psf, residual, model, gain, threshold, niter, work=None, stream=None):
+    """Hogbom minor cycle on one plane (residual updated in place, model
+    accumulated); returns the number of subtractions."""
+    ny, nx = residual.shape[-2:]
+    p = LR_F64 if residual.dtype == torch.float64 else LR_F32
+    n = lib().lr_hogbom_work_bytes(nx, ny)
+    if work is None or work.numel() < n:
+        work = torch.empty(n, dtype=torch.uint8, device=residual.device)
+    it = C.c_int32()
+    _check(lib().lr_hogbom(_ptr(psf), _ptr(residual), _ptr(model), nx, ny, p, gain, threshold,
+                           niter, C.byref(it), _ptr(work), work.numel(), _stream(stream)))
+    return it.value
