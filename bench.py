@@ -299,6 +299,7 @@ def image_bench(wl, form, steps, ev):
     import torch
     from paper_2508_17187_amd import lr
     from paper_2508_17187_amd import workload as W
+    from paper_2508_17187_amd.autograd import DegridOp
     from paper_2508_17187_amd.imaging import dirty_image, grid_correction, residual_image
     p = lr.PRECISIONS[form]
     cf = W.build_cf(wl, p)
@@ -313,9 +314,11 @@ def image_bench(wl, form, steps, ev):
     ix = torch.randint(g.nx // 4, 3 * g.nx // 4, (20,), generator=gen, device="cuda")
     model[:, :, iy, ix] = 0.5
     gcf = grid_correction(cf)
+    op = DegridOp(cf, v, p)
     out = {}
     for name, fn in (("dirty_image_ms", lambda: dirty_image(cf, v, p, gcf=gcf)),
-                     ("residual_image_ms", lambda: residual_image(cf, v, p, model, gcf=gcf))):
+                     ("residual_image_ms",
+                      lambda: residual_image(cf, v, p, model, gcf=gcf, op=op))):
         fn()
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
@@ -327,6 +330,22 @@ def image_bench(wl, form, steps, ev):
         out[name] = a.elapsed_time(b) / steps
     img, _ = dirty_image(cf, v, p, gcf=gcf)
     out["dirty_peak_jy"] = float(img[0, 0].max().item())
+    # PSF image and a minor cycle on the Stokes-I-like first plane
+    cdt = torch.complex128 if p == lr.LR_F64 else torch.complex64
+    psfg = torch.zeros((g.nplane, g.npol, g.ny, g.nx), dtype=cdt, device="cuda")
+    sw = torch.zeros((g.nplane, g.npol), dtype=torch.float64, device="cuda")
+    vp = v.with_(plan=None)
+    lr.lr_make_psf(cf, vp.with_(plan=lr.Plan(cf, vp, psf=True)), p, psfg, sumwt=sw)
+    from paper_2508_17187_amd.autograd import centred_ifft2
+    psf = lr.lr_image_normalize(cf, p, centred_ifft2(psfg).contiguous(), gcf[0], gcf[1], sw)
+    res = img[0, 0].contiguous()
+    model = torch.zeros_like(res)
+    niter = 1000
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it = lr.lr_hogbom(psf[0, 0].contiguous(), res, model, 0.1, 0.0, niter)
+    out["hogbom_iterations"] = it
+    out["hogbom_ms_per_iteration"] = 1e3 * (time.perf_counter() - t0) / max(it, 1)
     out["form"] = form
     return out
 

@@ -34,11 +34,13 @@ def dirty_image(cf, vis, precision, gcf=None, work=None):
     return lr.lr_image_normalize(cf, precision, img, gx, gy, sumwt), sumwt
 
 
-def residual_image(cf, vis, precision, model, gcf=None):
+def residual_image(cf, vis, precision, model, gcf=None, op=None):
     """Image of V - D F (Gamma I) for a real model image I [nplane, npol,
-    ny, nx] (Eq. ResIm); returns (image, sumwt)."""
+    ny, nx] (Eq. ResIm); returns (image, sumwt).  op: a DegridOp of the
+    same data to reuse across major cycles."""
     gx, gy = grid_correction(cf, device=vis.uvw.device) if gcf is None else gcf
-    op = DegridOp(cf, vis, precision)
+    if op is None:
+        op = DegridOp(cf, vis, precision)
     gamma = 1.0 / (gy[:, None] * gx[None, :])
     pred = op.degrid(centred_fft2((model * gamma).to(op.cdt)))
     return dirty_image(cf, vis.with_(vis=(vis.vis - pred).contiguous()), precision,
