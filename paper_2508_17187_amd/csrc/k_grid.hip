@@ -778,6 +778,9 @@ struct DegridArgs {
     int64_t pol_stride;
 };
 
+// Taps per lane whose loads are in flight together in the degridder.
+constexpr int kDegridTaps = 4;
+
 // One wavefront per group: lanes walk the footprint taps in row-major order,
 // four taps per lane in flight; the sub-kernel and the footprint's corner
 // cell (per pol) are scalar base addresses and a lane carries 32-bit
@@ -813,12 +816,12 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
     int goff = ty * row + tx * (int)(2 * sizeof(T));
     cpx<T> sum[NPOL];
     for (int p = 0; p < NPOL; ++p) sum[p] = {(T)0, (T)0};
-    for (int t0 = 0; t0 < SS; t0 += 256) {
-        Raw cr[4];
-        cpx<T> gv[4][NPOL];
-        bool ok[4];
-        int txs[4], tys[4];
-        for (int u = 0; u < 4; ++u) {
+    for (int t0 = 0; t0 < SS; t0 += 64 * kDegridTaps) {
+        Raw cr[kDegridTaps];
+        cpx<T> gv[kDegridTaps][NPOL];
+        bool ok[kDegridTaps];
+        int txs[kDegridTaps], tys[kDegridTaps];
+        for (int u = 0; u < kDegridTaps; ++u) {
             const int tap = t0 + u * 64 + lane;
             ok[u] = tap < SS;
             txs[u] = tx;
@@ -840,7 +843,7 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
                 goff += row - S * (int)(2 * sizeof(T));
             }
         }
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kDegridTaps; ++u) {
             if (!ok[u]) continue;
             cpx<T> cv = CFRaw<ST>::decode(cr[u], sc);
             if (cj) cv.y = -cv.y;
