@@ -814,16 +814,19 @@ struct DegridArgs {
     int64_t pol_stride;
 };
 
-// Taps per lane whose loads are in flight together in the degridder.
+// Taps per lane whose loads are in flight together in the degridder: 4, or
+// 8 with 4-byte (FP16 / BF16) kernel values, whose raw words take half the
+// registers.
 constexpr int kDegridTaps = 4;
 
 // One wavefront per group: lanes walk the footprint taps in row-major order,
-// four taps per lane in flight; the sub-kernel and the footprint's corner
-// cell (per pol) are scalar base addresses and a lane carries 32-bit
+// four or eight taps per lane in flight; the sub-kernel and the footprint's
+// corner cell (per pol) are scalar base addresses and a lane carries 32-bit
 // offsets, advanced by 64 taps at a time without division.
 template <typename T, int ST, int NPOL, bool PO>
 __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
     constexpr int E = CFRaw<ST>::bytes;
+    constexpr int NT = E <= 4 ? 2 * kDegridTaps : kDegridTaps;
     typedef typename CFRaw<ST>::R Raw;
     const int lane = threadIdx.x & 63;
     // consecutive groups (same plane, neighbouring footprints) run side by
@@ -852,12 +855,12 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
     int goff = ty * row + tx * (int)(2 * sizeof(T));
     cpx<T> sum[NPOL];
     for (int p = 0; p < NPOL; ++p) sum[p] = {(T)0, (T)0};
-    for (int t0 = 0; t0 < SS; t0 += 64 * kDegridTaps) {
-        Raw cr[kDegridTaps];
-        cpx<T> gv[kDegridTaps][NPOL];
-        bool ok[kDegridTaps];
-        int txs[kDegridTaps], tys[kDegridTaps];
-        for (int u = 0; u < kDegridTaps; ++u) {
+    for (int t0 = 0; t0 < SS; t0 += 64 * NT) {
+        Raw cr[NT];
+        cpx<T> gv[NT][NPOL];
+        bool ok[NT];
+        int txs[NT], tys[NT];
+        for (int u = 0; u < NT; ++u) {
             const int tap = t0 + u * 64 + lane;
             ok[u] = tap < SS;
             txs[u] = tx;
@@ -879,7 +882,7 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
                 goff += row - S * (int)(2 * sizeof(T));
             }
         }
-        for (int u = 0; u < kDegridTaps; ++u) {
+        for (int u = 0; u < NT; ++u) {
             if (!ok[u]) continue;
             cpx<T> cv = CFRaw<ST>::decode(cr[u], sc);
             if (cj) cv.y = -cv.y;
