@@ -226,6 +226,45 @@ def gridding_roofline(wl, form, r):
             "call_ms": r["grid_call_ms"]}
 
 
+def cf_cache_bench(wl, form):
+    """The CF cache on the W-projection table: build alone, build and write
+    to disk, load back from disk (page cache warm: the file was just
+    written) and a resident hit."""
+    import shutil
+    import tempfile
+    import torch
+    from paper_2508_17187_amd import cfcache
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import workload as W
+    p = lr.PRECISIONS[form]
+    g, s = W.grid_spec(wl.grid), W.cf_spec(wl.cf, p)
+
+    def timed(f):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = f()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    d = tempfile.mkdtemp(prefix="lrcf_")
+    try:
+        cf, t_build = timed(lambda: lr.lr_cf_build(g, dict(s)))
+        nbytes = cf.nbytes
+        del cf
+        c1 = cfcache.CFCache(d)
+        _, t_build_save = timed(lambda: c1.get(g, s))
+        del c1
+        c2 = cfcache.CFCache(d)
+        _, t_load = timed(lambda: c2.get(g, s))
+        _, t_hit = timed(lambda: c2.get(g, s))
+        assert c2.stats["loads"] == 1 and c2.stats["hits"] == 1
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    return {"table_bytes": int(nbytes), "build_s": t_build, "build_and_save_s": t_build_save,
+            "load_s": t_load, "load_gb_per_s": nbytes / t_load / 1e9, "hit_s": t_hit,
+            "form": form}
+
+
 def large_image_bench(steps, warmup, ev):
     """The large single image: all 1,293,926,400 samples of the 8 h
     observation streamed from pinned host memory in 13 chunks of 1e8
@@ -529,6 +568,9 @@ def main():
     log("residual image")
     images = image_bench(wl, args.form, args.steps, ev)
     log("  ", json.dumps(images))
+    log("CF cache")
+    cache = cf_cache_bench(wl, args.form)
+    log("  ", json.dumps(cache))
     hbm = None
     if args.ps:
         # the same data through the Standard kernel (PS, S = 7, O = 100, one
@@ -571,6 +613,7 @@ def main():
         "forms": res,
     }
     out["image"] = images
+    out["cf_cache"] = cache
     if hbm is not None:
         out["hbm_bound_workload"] = hbm
     if args.large:
