@@ -13,6 +13,9 @@ Layout
   native       ctypes binding of gridding.c (map, grid, degrid, psf, sumwt)
   imaging      image-plane helpers used by the pins: gcf, direct DFT,
                chi^2 and its gradient
+  hogbom       Hogbom minor cycle
+  calibration  diagonal G-Jones solve: ratio averages, update direction,
+               damped update, exit test
 
 Parity status: every function is pinned by a CPU test against something
 other than itself (closed forms, brute force, library routines, invariants);
