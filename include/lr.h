@@ -266,6 +266,57 @@ lr_status lr_image_normalize(const lr_cf *cf, lr_precision precision, const void
                              const double *gcf_x, const double *gcf_y, const double *sumwt,
                              void *out, lr_stream stream);
 
+/* ---- calibration: diagonal G-Jones (the calibration section) -------------- */
+
+/* PreSolvePrep (Eq. VAvg): ratio averages of observed to model visibilities
+ * per solution interval, parallel hand and baseline, as inputs of the gain
+ * solve.  For every kept sample (weight > 0, model != 0, ant1 != ant2, row
+ * and channel inside an interval) of baseline (i, j):
+ *     X[s][q][i][j] = sum W V conj(M) / sum W |M|^2,
+ *     w[s][q][i][j] = sum W |M|^2,
+ * the inverse-variance mean of the ratios V / M, so that X estimates
+ * g_i conj(g_j) (the paper's sum of ratios normalised by its weights).
+ * X[s][q][j][i] = conj(X[s][q][i][j]); rows j-i and i-j enter the same
+ * average; the diagonal and baselines without samples are 0.
+ *   vis_obs, vis_model  [nrow][nchan][npol] complex (complex128 with
+ *                       LR_F64, complex64 with LR_F32), device
+ *   weight              [nrow][nchan][npol] float64 / float32, device; NULL
+ *                       for unit weights
+ *   ant1, ant2          [nrow] int32 antenna ids, device; ids outside
+ *                       [0, nant) are ignored
+ *   row_sol [nrow], chan_sol [nchan]  int32 interval of each row / channel,
+ *                       device; < 0 or >= n_tsol / n_fsol: not used
+ *   rows_per_step       rows of one dump of time-major data (the number of
+ *                       baselines), or 1: only the speed depends on it
+ *   X                   complex128 [n_tsol][n_fsol][npar][nant][nant],
+ *   w                   float64 of the same shape, device, overwritten;
+ *                       s = t_sol * n_fsol + f_sol; npar = 2 parallel hands
+ *                       (XX, YY of 4 correlations; both of 2), 1 for npol 1
+ * Sums in FP64.  LR_E_ARG for NULL pointers or sizes out of range,
+ * LR_E_DTYPE for a precision other than LR_F64 / LR_F32. */
+lr_status lr_cal_vavg(int64_t nrow, int32_t nchan, int32_t npol, lr_precision precision,
+                      const void *vis_obs, const void *vis_model, const void *weight,
+                      const int32_t *ant1, const int32_t *ant2, int32_t nant,
+                      const int32_t *row_sol, int32_t n_tsol, const int32_t *chan_sol,
+                      int32_t n_fsol, int32_t rows_per_step, double *X, double *w,
+                      lr_stream stream);
+
+/* UpdateDir, ModelUpdate and ExitCriteria (Eqs. CalUpdateDir,
+ * CalUpdateModel): for each of n_problems independent problems (X, w of
+ * lr_cal_vavg, consecutive [nant][nant] matrices) iterate, from the gains
+ * in g (complex128 [n_problems][nant], device, in / out),
+ *     dg_i = sum_{j != i} g_j X_ij w_ij / sum_{j != i} |g_j|^2 w_ij
+ *     g_i <- (1 - alpha) g_i + alpha dg_i      (all i from the same iterate;
+ *                                              no weight: g_i unchanged)
+ * until max_i |change| < delta or max_iter iterations.  iterations
+ * (int32 [n_problems]) and change (float64 [n_problems]: the last max
+ * |change|) receive the outcome, device.  FP64.  LR_E_ARG for NULL
+ * pointers, nant outside [1, 2048], alpha outside (0, 1], delta < 0 or
+ * max_iter < 0. */
+lr_status lr_cal_solve(const double *X, const double *w, int32_t nant, int64_t n_problems,
+                       double alpha, double delta, int32_t max_iter, double *g,
+                       int32_t *iterations, double *change, lr_stream stream);
+
 /* ---- minor cycle (ModelUpdate of the imaging section) -------------------- */
 
 /* Hogbom minor cycle on one image plane [ny][nx] (float64 with LR_F64,

@@ -583,6 +583,45 @@ lr_status lr_hogbom(const void *psf, void *residual, void *model, int32_t nx, in
     return LR_OK;
 }
 
+lr_status lr_cal_vavg(int64_t nrow, int32_t nchan, int32_t npol, lr_precision precision,
+                      const void *vis_obs, const void *vis_model, const void *weight,
+                      const int32_t *ant1, const int32_t *ant2, int32_t nant,
+                      const int32_t *row_sol, int32_t n_tsol, const int32_t *chan_sol,
+                      int32_t n_fsol, int32_t rows_per_step, double *X, double *w,
+                      lr_stream stream) {
+    if (precision != LR_F64 && precision != LR_F32)
+        return fail(LR_E_DTYPE, "visibilities are complex128 (LR_F64) or complex64 (LR_F32)");
+    if (!X || !w || !chan_sol) return fail(LR_E_ARG, "NULL argument");
+    if (nrow > 0 && (!vis_obs || !vis_model || !ant1 || !ant2 || !row_sol))
+        return fail(LR_E_ARG, "NULL argument");
+    if (nrow < 0 || nchan < 1 || (npol != 1 && npol != 2 && npol != 4))
+        return fail(LR_E_ARG, "bad shape nrow %lld nchan %d npol %d", (long long)nrow, nchan, npol);
+    if (nant < 1 || nant > 65535 || n_tsol < 1 || n_fsol < 1 || rows_per_step < 1)
+        return fail(LR_E_ARG, "nant, interval counts and rows_per_step must be positive");
+    const int64_t npar = npol == 1 ? 1 : 2;
+    const double cells = (double)n_tsol * n_fsol * npar * nant * nant;
+    if (cells > 4.0e9) return fail(LR_E_ARG, "output of %.3g matrix cells is too large", cells);
+    CalVavg c{vis_obs, vis_model, weight, ant1, ant2, row_sol, chan_sol, nrow, nchan, npol,
+              nant, n_tsol, n_fsol, rows_per_step, (int32_t)precision, X, w};
+    hipError_t e = launch_cal_vavg(c, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "cal_vavg");
+    return LR_OK;
+}
+
+lr_status lr_cal_solve(const double *X, const double *w, int32_t nant, int64_t n_problems,
+                       double alpha, double delta, int32_t max_iter, double *g,
+                       int32_t *iterations, double *change, lr_stream stream) {
+    if (!X || !w || !g || !iterations || !change) return fail(LR_E_ARG, "NULL argument");
+    if (nant < 1 || nant > 2048) return fail(LR_E_ARG, "nant must be in [1, 2048]");
+    if (n_problems < 0 || n_problems > 0x7fffffff) return fail(LR_E_ARG, "bad n_problems");
+    if (!(alpha > 0.0 && alpha <= 1.0)) return fail(LR_E_ARG, "alpha must be in (0, 1]");
+    if (!(delta >= 0.0) || max_iter < 0) return fail(LR_E_ARG, "delta < 0 or max_iter < 0");
+    hipError_t e = launch_cal_solve(X, w, nant, n_problems, alpha, delta, max_iter, g,
+                                    iterations, change, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "cal_solve");
+    return LR_OK;
+}
+
 lr_status lr_plan_info(const lr_plan *plan, int64_t *n_groups, int64_t *n_kept,
                        int64_t *n_pairs, int64_t *taps) {
     if (!plan) return fail(LR_E_ARG, "plan is NULL");

@@ -96,4 +96,17 @@ hipError_t launch_hogbom(void *res, const void *psf, void *model, int32_t nx, in
                          int precision, double gain, double threshold, int32_t niter,
                          void *work, int32_t *iters, hipStream_t s);
 
+// ---- calibration (k_cal.hip) ----------------------------------------------------
+struct CalVavg {
+    const void *obs, *mod, *weight;
+    const int32_t *ant1, *ant2, *row_sol, *chan_sol;
+    int64_t nrow;
+    int32_t nchan, npol, nant, n_tsol, n_fsol, rows_per_step, precision;
+    double *X, *w;
+};
+hipError_t launch_cal_vavg(const CalVavg &c, hipStream_t s);
+hipError_t launch_cal_solve(const double *X, const double *w, int32_t nant, int64_t n_prob,
+                            double alpha, double delta, int32_t max_iter, double *g,
+                            int32_t *iterations, double *change, hipStream_t s);
+
 }  // namespace lr

@@ -34,14 +34,22 @@ def dirty_image(cf, vis, precision, gcf=None, work=None):
     return lr.lr_image_normalize(cf, precision, img, gx, gy, sumwt), sumwt
 
 
+def predict(cf, vis, precision, model, gcf=None, op=None):
+    """Model visibilities D F (Gamma I) of a real model image I [nplane,
+    npol, ny, nx] (Eq. VMod, with the grid correction Gamma = 1 / (gcf_x
+    gcf_y) of Eq. ImChisq), [nrow, nchan, npol]; flagged samples are 0."""
+    gx, gy = grid_correction(cf, device=vis.uvw.device) if gcf is None else gcf
+    if op is None:
+        op = DegridOp(cf, vis, precision)
+    gamma = 1.0 / (gy[:, None] * gx[None, :])
+    return op.degrid(centred_fft2((model * gamma).to(op.cdt)))
+
+
 def residual_image(cf, vis, precision, model, gcf=None, op=None):
     """Image of V - D F (Gamma I) for a real model image I [nplane, npol,
     ny, nx] (Eq. ResIm); returns (image, sumwt).  op: a DegridOp of the
     same data to reuse across major cycles."""
     gx, gy = grid_correction(cf, device=vis.uvw.device) if gcf is None else gcf
-    if op is None:
-        op = DegridOp(cf, vis, precision)
-    gamma = 1.0 / (gy[:, None] * gx[None, :])
-    pred = op.degrid(centred_fft2((model * gamma).to(op.cdt)))
+    pred = predict(cf, vis, precision, model, gcf=(gx, gy), op=op)
     return dirty_image(cf, vis.with_(vis=(vis.vis - pred).contiguous()), precision,
                        gcf=(gx, gy))

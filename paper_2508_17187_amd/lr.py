@@ -82,6 +82,13 @@ EXPORTS = {
                            C.c_size_t, C.c_void_p]),
     "lr_debug_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "lr_gcf": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "lr_cal_vavg": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int, C.c_void_p, C.c_void_p,
+                              C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                              C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
+                              C.c_void_p, C.c_void_p]),
+    "lr_cal_solve": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int32, C.c_int64, C.c_double,
+                               C.c_double, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                               C.c_void_p]),
     "lr_hogbom_work_bytes": (C.c_size_t, [C.c_int32, C.c_int32]),
     "lr_hogbom": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32, C.c_int,
                             C.c_double, C.c_double, C.c_int32, C.c_void_p, C.c_void_p,
@@ -425,3 +432,47 @@ def lr_hogbom(psf, residual, model, gain, threshold, niter, work=None, stream=No
     _check(lib().lr_hogbom(_ptr(psf), _ptr(residual), _ptr(model), nx, ny, p, gain, threshold,
                            niter, C.byref(it), _ptr(work), work.numel(), _stream(stream)))
     return it.value
+
+
+def lr_cal_vavg(vis_obs, vis_model, weight, ant1, ant2, nant, row_sol, n_tsol, chan_sol,
+                n_fsol, rows_per_step=1, stream=None):
+    """Ratio averages of Eq. VAvg: (X complex128, w float64), each
+    [n_tsol, n_fsol, npar, nant, nant], from [nrow, nchan, npol] device
+    tensors (complex128 / float64, or complex64 / float32) and int32 device
+    antenna ids and interval indices."""
+    nrow, nchan, npol = vis_obs.shape
+    p = LR_F64 if vis_obs.dtype == torch.complex128 else LR_F32
+    cdt, rdt = _vis_dtype(p)
+    for t, dt in ((vis_obs, cdt), (vis_model, cdt), (weight, rdt), (ant1, torch.int32),
+                  (ant2, torch.int32), (row_sol, torch.int32), (chan_sol, torch.int32)):
+        if t is not None and (t.dtype != dt or not t.is_contiguous()):
+            raise LRError(LR_E_DTYPE, "expected contiguous %s, got %s" % (dt, t.dtype))
+    if vis_model.shape != vis_obs.shape or (weight is not None and weight.shape != vis_obs.shape):
+        raise LRError(LR_E_ARG, "vis_obs, vis_model and weight differ in shape")
+    npar = 1 if npol == 1 else 2
+    dev = vis_obs.device
+    X = torch.empty((n_tsol, n_fsol, npar, nant, nant), dtype=torch.complex128, device=dev)
+    w = torch.empty((n_tsol, n_fsol, npar, nant, nant), dtype=torch.float64, device=dev)
+    _check(lib().lr_cal_vavg(nrow, nchan, npol, p, _ptr(vis_obs), _ptr(vis_model), _ptr(weight),
+                             _ptr(ant1), _ptr(ant2), nant, _ptr(row_sol), n_tsol,
+                             _ptr(chan_sol), n_fsol, rows_per_step, _ptr(X), _ptr(w),
+                             _stream(stream)))
+    return X, w
+
+
+def lr_cal_solve(X, w, g0=None, alpha=0.5, delta=1e-10, max_iter=500, stream=None):
+    """Gains of every problem in X, w (lr_cal_vavg's outputs, any leading
+    shape): returns (g complex128 [..., nant], iterations int32 [...],
+    last max change float64 [...]).  g0: starting gains (default 1)."""
+    nant = X.shape[-1]
+    lead = X.shape[:-2]
+    n = int(np.prod(lead)) if len(lead) else 1
+    if g0 is None:
+        g = torch.ones(lead + (nant,), dtype=torch.complex128, device=X.device)
+    else:
+        g = g0.to(torch.complex128).clone().contiguous()
+    it = torch.empty(lead, dtype=torch.int32, device=X.device)
+    ch = torch.empty(lead, dtype=torch.float64, device=X.device)
+    _check(lib().lr_cal_solve(_ptr(X.contiguous()), _ptr(w.contiguous()), nant, n, alpha, delta,
+                              max_iter, _ptr(g), _ptr(it), _ptr(ch), _stream(stream)))
+    return g, it, ch
