@@ -265,6 +265,97 @@ def cf_cache_bench(wl, form):
             "form": form}
 
 
+def calibration_bench(wl, form, steps):
+    """Diagonal G-Jones solve on the W-projection data: model visibilities of
+    the sky's sources predicted by the degridder, observed data = those
+    times known per-antenna gains plus noise, 10 time x 4 frequency
+    intervals, both parallel hands (80 problems of 27 antennas).  Times the
+    ratio averages (one lr_cal_vavg call: clear, sums, finalise) and the
+    solve; the bytes rated are the observed, model and weight records read
+    once plus the antenna ids and intervals of every row."""
+    import numpy as np
+    import torch
+    from paper_2508_17187_amd import calibration as cal
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import workload as W
+    from paper_2508_17187_amd.imaging import predict
+    p = lr.PRECISIONS[form]
+    cf = W.build_cf(wl, p)
+    v = W.device_vis(wl, p)
+    g = wl.grid
+    # model image: the sky's point sources that fall in the inner half of
+    # the image, at their nearest pixels, and a few fixed ones
+    model = torch.zeros((g.nplane, g.npol, g.ny, g.nx), dtype=torch.float64, device="cuda")
+    px = np.rint(wl.sky.l / g.cell_l).astype(int) + g.nx // 2
+    py = np.rint(wl.sky.m / g.cell_m).astype(int) + g.ny // 2
+    pts = [(x, y, f) for x, y, f in zip(px, py, wl.sky.flux)
+           if g.nx // 4 <= x < 3 * g.nx // 4 and g.ny // 4 <= y < 3 * g.ny // 4]
+    pts += [(g.nx // 2 + 37 * k, g.ny // 2 - 29 * k, 1.0 / (1 + k)) for k in range(5)]
+    for x, y, f in pts:
+        for pp in (0, 3):
+            model[0, pp, y, x] += f
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    vmod = predict(cf, v, p, model)
+    torch.cuda.synchronize()
+    t_pred = time.perf_counter() - t0
+    nant = int(max(wl.obs.ant1.max(), wl.obs.ant2.max())) + 1
+    nrow, nchan = wl.obs.nrow, wl.obs.nchan
+    nbl = nant * (nant - 1) // 2
+    n_tsol, n_fsol = 10, 4
+    a1 = torch.as_tensor(wl.obs.ant1.astype(np.int32), device="cuda")
+    a2 = torch.as_tensor(wl.obs.ant2.astype(np.int32), device="cuda")
+    ndump = nrow // nbl
+    row_sol = torch.as_tensor((np.arange(nrow) // nbl * n_tsol // ndump).astype(np.int32),
+                              device="cuda")
+    chan_sol = torch.as_tensor((np.arange(nchan) * n_fsol // nchan).astype(np.int32),
+                               device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(7007)
+    amp = 1.0 + 0.1 * torch.randn((n_tsol, n_fsol, 2, nant), generator=gen, device="cuda",
+                                  dtype=torch.float64)
+    ph = 3.0 * (torch.rand((n_tsol, n_fsol, 2, nant), generator=gen, device="cuda",
+                           dtype=torch.float64) - 0.5)
+    gt = torch.polar(amp, ph)
+    rs, cs = row_sol.long(), chan_sol.long()
+    vobs = vmod.clone()
+    for q, pp in enumerate((0, 3)):
+        gq = gt[:, :, q]                                   # [n_tsol, n_fsol, nant]
+        gi = gq[rs][:, cs, :].gather(2, a1.long()[:, None, None].expand(nrow, nchan, 1))[..., 0]
+        gj = gq[rs][:, cs, :].gather(2, a2.long()[:, None, None].expand(nrow, nchan, 1))[..., 0]
+        noise = 0.01 * torch.complex(torch.randn((nrow, nchan), generator=gen, device="cuda"),
+                                     torch.randn((nrow, nchan), generator=gen, device="cuda"))
+        vobs[:, :, pp] = (gi * torch.conj(gj)).to(vmod.dtype) * vmod[:, :, pp] + noise.to(vmod.dtype)
+    vobs = vobs.contiguous()
+    run = lambda: lr.lr_cal_vavg(vobs, vmod, v.weight, a1, a2, nant, row_sol, n_tsol, chan_sol,
+                                 n_fsol, rows_per_step=nbl)
+    for _ in range(2):
+        X, w = run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        X, w = run()
+    torch.cuda.synchronize()
+    t_vavg = (time.perf_counter() - t0) / steps
+    t0 = time.perf_counter()
+    gs, it, ch = lr.lr_cal_solve(X, w, alpha=0.5, delta=1e-10, max_iter=1000)
+    torch.cuda.synchronize()
+    t_solve = time.perf_counter() - t0
+    # gain products against the truth (the data cannot see a common phase)
+    P = gs[..., :, None] * torch.conj(gs[..., None, :])
+    T = gt[..., :, None] * torch.conj(gt[..., None, :])
+    off = ~torch.eye(nant, dtype=torch.bool, device="cuda")
+    err = float((P - T).abs()[..., off].max())
+    cplx = 16 if p == lr.LR_F64 else 8
+    byts = nrow * nchan * 4 * (2 * cplx + cplx // 2) + nrow * 12 + nchan * 4
+    return {"form": form, "n_problems": int(it.numel()), "nant": nant, "predict_ms": 1e3 * t_pred,
+            "vavg_ms": 1e3 * t_vavg, "vavg_gb_per_s": byts / t_vavg / 1e9,
+            "vavg_hbm_frac": byts / t_vavg / HBM_PEAK,
+            "solve_ms": 1e3 * t_solve, "iterations_max": int(it.max()),
+            "iterations_mean": float(it.float().mean()), "gain_product_max_error": err,
+            "noise_per_sample": 0.01}
+
+
 def large_image_bench(steps, warmup, ev):
     """The large single image: all 1,293,926,400 samples of the 8 h
     observation streamed from pinned host memory in 13 chunks of 1e8
@@ -571,6 +662,9 @@ def main():
     log("CF cache")
     cache = cf_cache_bench(wl, args.form)
     log("  ", json.dumps(cache))
+    log("calibration")
+    calib = calibration_bench(wl, args.form, args.steps)
+    log("  ", json.dumps(calib))
     hbm = None
     if args.ps:
         # the same data through the Standard kernel (PS, S = 7, O = 100, one
@@ -614,6 +708,7 @@ def main():
     }
     out["image"] = images
     out["cf_cache"] = cache
+    out["calibration"] = calib
     if hbm is not None:
         out["hbm_bound_workload"] = hbm
     if args.large:

@@ -39,40 +39,77 @@ __global__ __launch_bounds__(256) void k_cal_vavg(VavgArgs a) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t c = t % a.L;
     const int64_t blk = t / a.L;
-    if (blk >= a.n_cols_blocks) return;
+    // threads past the work stay (idle) for the wave-wide flushes
+    const bool live = blk < a.n_cols_blocks;
     const int ch = (int)(c % a.nchan);
     const int64_t slot = c / a.nchan;
-    const int fs = a.chan_sol[ch];
-    if (fs < 0 || fs >= a.n_fsol) return;
+    // lanes of a channel outside every interval stay for the wave-wide
+    // flushes but never hold a bin
+    const int fs0 = a.chan_sol[ch];
+    const bool chan_ok = fs0 >= 0 && fs0 < a.n_fsol;
+    const int fs = chan_ok ? fs0 : 0;
     const int64_t m0 = blk * a.steps_per_thread;
     const int64_t nn = (int64_t)a.nant * a.nant;
     int64_t bin = -1;                       // bin of hand 0; hand q adds q * nn
     double nr[NPAR], ni[NPAR], dw[NPAR];
     for (int q = 0; q < NPAR; ++q) nr[q] = ni[q] = dw[q] = 0.0;
-    auto flush = [&]() {
-        for (int q = 0; q < NPAR; ++q) {
-            if (dw[q] != 0.0) {
-                const int64_t b = bin + q * nn;
-                atomicAdd(&a.X[2 * b], nr[q]);
-                atomicAdd(&a.X[2 * b + 1], ni[q]);
-                atomicAdd(&a.w[b], dw[q]);
+    const int lane = threadIdx.x & 63;
+    // Lanes whose bin closes add their sums to it.  Neighbouring lanes (the
+    // channels of one frequency interval of one baseline) usually close the
+    // same bin at the same step: a segmented sum over runs of equal bins
+    // leaves one atomic per run.  Every lane of the wavefront takes part.
+    auto flush = [&](bool closing) {
+        // runs of lanes closing the same bin; every other lane a run of its
+        // own (a bin closed by two separate runs gets one atomic per run)
+        const int64_t key = closing && bin >= 0 ? bin : -1 - (int64_t)lane;
+        const int64_t kp = __shfl_up(key, 1);
+        const uint64_t heads = __ballot(lane == 0 || kp != key);
+        const int seg = __popcll(heads & ((2ull << lane) - 1));
+        for (int off = 1; off < 64; off <<= 1) {
+            const int so = __shfl_up(seg, off);
+            const bool take = lane >= off && so == seg;
+            for (int q = 0; q < NPAR; ++q) {
+                const double r = __shfl_up(nr[q], off), im = __shfl_up(ni[q], off),
+                             d = __shfl_up(dw[q], off);
+                if (take && closing) {
+                    nr[q] += r;
+                    ni[q] += im;
+                    dw[q] += d;
+                }
             }
-            nr[q] = ni[q] = dw[q] = 0.0;
+        }
+        const int sn = __shfl_down(seg, 1);
+        const bool last = lane == 63 || sn != seg;
+        if (closing) {
+            for (int q = 0; q < NPAR; ++q) {
+                if (last && bin >= 0 && dw[q] != 0.0) {
+                    const int64_t b = bin + q * nn;
+                    atomicAdd(&a.X[2 * b], nr[q]);
+                    atomicAdd(&a.X[2 * b + 1], ni[q]);
+                    atomicAdd(&a.w[b], dw[q]);
+                }
+                nr[q] = ni[q] = dw[q] = 0.0;
+            }
         }
     };
     for (int s = 0; s < a.steps_per_thread; ++s) {
         const int64_t row = slot + (m0 + s) * a.rows_per_step;
-        if (row >= a.nrow) break;
-        const int i = a.ant1[row], j = a.ant2[row], ts = a.row_sol[row];
-        // autocorrelations, rows outside every interval and ids out of range
-        if (i == j || ts < 0 || ts >= a.n_tsol || (unsigned)i >= (unsigned)a.nant ||
-            (unsigned)j >= (unsigned)a.nant)
-            continue;
-        const int64_t b = ((((int64_t)ts * a.n_fsol + fs) * NPAR) * a.nant + i) * a.nant + j;
-        if (b != bin) {
-            if (bin >= 0) flush();
-            bin = b;
+        const bool in = live && chan_ok && row < a.nrow;
+        int i = 0, j = 0, ts = -1;
+        if (in) {
+            i = a.ant1[row];
+            j = a.ant2[row];
+            ts = a.row_sol[row];
         }
+        // autocorrelations, rows outside every interval and ids out of range
+        const bool use = in && i != j && ts >= 0 && ts < a.n_tsol &&
+                         (unsigned)i < (unsigned)a.nant && (unsigned)j < (unsigned)a.nant;
+        const int64_t b =
+            use ? ((((int64_t)ts * a.n_fsol + fs) * NPAR) * a.nant + i) * a.nant + j : bin;
+        const bool closing = use && b != bin;
+        if (__any(closing)) flush(closing);
+        if (closing) bin = b;
+        if (!use) continue;
         const int64_t e = (row * a.nchan + ch) * a.npol;
         const T *ov = (const T *)a.obs + 2 * e;
         const T *mv = (const T *)a.mod + 2 * e;
@@ -89,7 +126,7 @@ __global__ __launch_bounds__(256) void k_cal_vavg(VavgArgs a) {
             dw[q] += W * (mr * mr + mi * mi);
         }
     }
-    if (bin >= 0) flush();
+    flush(bin >= 0);
 }
 
 __global__ void k_cal_finalize(double *X, double *w, int32_t nant, int64_t n_mat) {
@@ -149,7 +186,7 @@ hipError_t launch_cal_vavg(const CalVavg &c, hipStream_t s) {
         a.n_fsol = c.n_fsol;
         a.npar = npar;
         a.rows_per_step = c.rows_per_step;
-        a.steps_per_thread = 64;
+        a.steps_per_thread = 16;
         a.L = (int64_t)c.rows_per_step * c.nchan;
         const int64_t steps = (c.nrow + c.rows_per_step - 1) / c.rows_per_step;
         a.n_cols_blocks = (steps + a.steps_per_thread - 1) / a.steps_per_thread;

@@ -111,6 +111,19 @@ def test_vavg_matches_oracle(npol, f64):
         assert np.array_equal(Xg, np.conj(np.swapaxes(Xg, -1, -2)))
 
 
+def test_vavg_interleaved_intervals():
+    """Frequency intervals that interleave channels, so that equal bins are
+    not neighbours: same averages as the oracle."""
+    d = dataset(seed=175)
+    d["chan_sol"] = np.array([1, 0, 1, 0, -1, 1], np.int32)
+    t = to_dev(d, True)
+    Xo, wo = oracle_vavg(d, t)
+    for rps in (d["nbl"], 1):
+        X, w = gpu_vavg(d, t, rps)
+        torch.cuda.synchronize()
+        assert rel(X.cpu().numpy(), Xo) < 1e-13 and rel(w.cpu().numpy(), wo) < 1e-13
+
+
 def test_ids_out_of_range_are_ignored():
     d = dataset(seed=170)
     t = to_dev(d, True)
