@@ -122,3 +122,41 @@ def test_binding_fails_loudly_without_the_library(L, monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(ImportError):
         L.lib()
+
+
+def test_calibration_calls_validate_on_the_host(L):
+    """lr_cal_vavg / lr_cal_solve reject malformed calls with the documented
+    status before launching anything (fake non-NULL pointers are never
+    dereferenced on these paths)."""
+    lib = L.lib()
+    p = C.c_void_p(0x1000)
+
+    def vavg(nrow=10, nchan=4, npol=4, prec=L.LR_F32, nant=5, n_tsol=1, n_fsol=1, rps=1,
+             X=p, w=p, obs=p):
+        return lib.lr_cal_vavg(nrow, nchan, npol, prec, obs, p, None, p, p, nant, p, n_tsol, p,
+                               n_fsol, rps, X, w, None)
+
+    assert vavg(prec=L.LR_F32_CF16) == L.LR_E_DTYPE
+    assert vavg(X=None) == L.LR_E_ARG
+    assert vavg(obs=None) == L.LR_E_ARG
+    assert vavg(npol=3) == L.LR_E_ARG
+    assert vavg(nchan=0) == L.LR_E_ARG
+    assert vavg(nrow=-1) == L.LR_E_ARG
+    assert vavg(nant=0) == L.LR_E_ARG
+    assert vavg(n_tsol=0) == L.LR_E_ARG
+    assert vavg(rps=0) == L.LR_E_ARG
+    assert vavg(nant=60000, n_tsol=100) == L.LR_E_ARG          # output too large
+    it = C.c_void_p(0x2000)
+
+    def solve(nant=5, n=3, alpha=0.5, delta=1e-9, max_iter=10, g=p):
+        return lib.lr_cal_solve(p, p, nant, n, alpha, delta, max_iter, g, it, it, None)
+
+    assert solve(g=None) == L.LR_E_ARG
+    assert solve(nant=0) == L.LR_E_ARG
+    assert solve(nant=2049) == L.LR_E_ARG
+    assert solve(alpha=0.0) == L.LR_E_ARG
+    assert solve(alpha=1.5) == L.LR_E_ARG
+    assert solve(delta=-1.0) == L.LR_E_ARG
+    assert solve(max_iter=-1) == L.LR_E_ARG
+    assert solve(n=-1) == L.LR_E_ARG
+    assert b"n_problems" in lib.lr_last_error()
