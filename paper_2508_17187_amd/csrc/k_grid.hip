@@ -186,6 +186,36 @@ struct CFRaw<LR_F32_CFBF16> {
     }
 };
 
+// Real tables (no A term, no w-dependence): only the real word of each
+// stored pair is loaded, and a tap costs two FMAs per polarisation instead
+// of four (the imaginary parts are rounding noise, below 1e-16 relative).
+template <int ST>
+struct CFReal;
+template <>
+struct CFReal<LR_F64> {
+    typedef double R;
+    __device__ static double decode(R v, float) { return v; }
+};
+template <>
+struct CFReal<LR_F32> {
+    typedef float R;
+    __device__ static float decode(R v, float) { return v; }
+};
+template <>
+struct CFReal<LR_F32_CF16> {
+    typedef uint16_t R;
+    __device__ static float decode(R b, float sc) {
+        _Float16 x;
+        __builtin_memcpy(&x, &b, 2);
+        return (float)x * sc;
+    }
+};
+template <>
+struct CFReal<LR_F32_CFBF16> {
+    typedef uint16_t R;
+    __device__ static float decode(R b, float sc) { return __uint_as_float((uint32_t)b << 16) * sc; }
+};
+
 // Wave-uniform copies of values that are the same in every lane.
 __device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
 __device__ __forceinline__ int64_t uni64(int64_t v) {
@@ -604,11 +634,11 @@ constexpr int kWaitVm0 = 0x0F70;
 // items of a chunk as ballot bits, 64 per word
 constexpr int kMaskWords = (kChunkMax + 63) / 64;
 
-template <typename T, int ST, int NPOL, bool PO, bool PSF>
+template <typename T, int ST, int NPOL, bool PO, bool PSF, bool RE>
 __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     constexpr int B = kItemBatch;
     constexpr int E = CFRaw<ST>::bytes;
-    typedef typename CFRaw<ST>::R Raw;
+    typedef typename std::conditional<RE, typename CFReal<ST>::R, typename CFRaw<ST>::R>::type Raw;
     __shared__ TileItem items[kChunkMax];
     __shared__ cpx<T> avs[kChunkMax * NPOL];
     __shared__ GroupMeta gms[PO ? kChunkMax : 1];
@@ -720,13 +750,21 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
             for (int p = 0; p < NPOL; ++p) av[p] = avs[t * NPOL + p];
             for (int j = 0; j < 4; ++j) {
                 if (!ok[b][j]) continue;
-                cpx<T> cw = CFRaw<ST>::decode(cv[b][j], scs[b]);
-                if (cj) cw.y = -cw.y;
-                if (PO) {
-                    const int h = items[t].h;
-                    cw = cmul(cw, phasor<T>(gms[t], dxs[b] - h, rs[b] + j - h, a.cf.O));
+                if constexpr (RE) {
+                    const T c = CFReal<ST>::decode(cv[b][j], scs[b]);
+                    for (int p = 0; p < NPOL; ++p) {
+                        acc[j][p].x = fma(c, av[p].x, acc[j][p].x);
+                        acc[j][p].y = fma(c, av[p].y, acc[j][p].y);
+                    }
+                } else {
+                    cpx<T> cw = CFRaw<ST>::decode(cv[b][j], scs[b]);
+                    if (cj) cw.y = -cw.y;
+                    if (PO) {
+                        const int h = items[t].h;
+                        cw = cmul(cw, phasor<T>(gms[t], dxs[b] - h, rs[b] + j - h, a.cf.O));
+                    }
+                    for (int p = 0; p < NPOL; ++p) cmac(acc[j][p], cw, av[p]);
                 }
-                for (int p = 0; p < NPOL; ++p) cmac(acc[j][p], cw, av[p]);
             }
         }
         // every load of the batch has landed (rows that no lane needed were
@@ -823,11 +861,11 @@ constexpr int kDegridTaps = 4;
 // four or eight taps per lane in flight; the sub-kernel and the footprint's
 // corner cell (per pol) are scalar base addresses and a lane carries 32-bit
 // offsets, advanced by 64 taps at a time without division.
-template <typename T, int ST, int NPOL, bool PO>
+template <typename T, int ST, int NPOL, bool PO, bool RE>
 __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
     constexpr int E = CFRaw<ST>::bytes;
     constexpr int NT = E <= 4 ? 2 * kDegridTaps : kDegridTaps;
-    typedef typename CFRaw<ST>::R Raw;
+    typedef typename std::conditional<RE, typename CFReal<ST>::R, typename CFRaw<ST>::R>::type Raw;
     const int lane = threadIdx.x & 63;
     // consecutive groups (same plane, neighbouring footprints) run side by
     // side across the XCDs, which share the last-level cache
@@ -884,10 +922,18 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
         }
         for (int u = 0; u < NT; ++u) {
             if (!ok[u]) continue;
-            cpx<T> cv = CFRaw<ST>::decode(cr[u], sc);
-            if (cj) cv.y = -cv.y;
-            if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
-            for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
+            if constexpr (RE) {
+                const T c = CFReal<ST>::decode(cr[u], sc);
+                for (int p = 0; p < NPOL; ++p) {
+                    sum[p].x = fma(c, gv[u][p].x, sum[p].x);
+                    sum[p].y = fma(c, gv[u][p].y, sum[p].y);
+                }
+            } else {
+                cpx<T> cv = CFRaw<ST>::decode(cr[u], sc);
+                if (cj) cv.y = -cv.y;
+                if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
+                for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
+            }
         }
         __builtin_amdgcn_s_waitcnt(kWaitVm0);
     }
@@ -903,10 +949,10 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
 // wavefront), four taps per lane in flight, and reduce over their 16 lanes.
 constexpr int kDegridSmallH = 7;
 
-template <typename T, int ST, int NPOL, bool PO>
+template <typename T, int ST, int NPOL, bool PO, bool RE>
 __global__ __launch_bounds__(256) void k_degrid_small(DegridArgs a) {
     constexpr int E = CFRaw<ST>::bytes;
-    typedef typename CFRaw<ST>::R Raw;
+    typedef typename std::conditional<RE, typename CFReal<ST>::R, typename CFRaw<ST>::R>::type Raw;
     const int sub = threadIdx.x & 15;
     const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
     const bool live = g < a.n_groups;
@@ -942,10 +988,18 @@ __global__ __launch_bounds__(256) void k_degrid_small(DegridArgs a) {
             }
             for (int u = 0; u < 4; ++u) {
                 if (t0 + u * 16 + sub >= SS) continue;
-                cpx<T> cv = CFRaw<ST>::decode(cr[u], gm.sc);
-                if (gm.conj) cv.y = -cv.y;
-                if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
-                for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
+                if constexpr (RE) {
+                    const T c = CFReal<ST>::decode(cr[u], gm.sc);
+                    for (int p = 0; p < NPOL; ++p) {
+                        sum[p].x = fma(c, gv[u][p].x, sum[p].x);
+                        sum[p].y = fma(c, gv[u][p].y, sum[p].y);
+                    }
+                } else {
+                    cpx<T> cv = CFRaw<ST>::decode(cr[u], gm.sc);
+                    if (gm.conj) cv.y = -cv.y;
+                    if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
+                    for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
+                }
             }
         }
     }
@@ -1052,11 +1106,14 @@ static hipError_t grid_t(const TileArgs &ta, int64_t n_blocks, bool po, bool psf
                          hipStream_t s) {
     dim3 grd((unsigned)n_blocks), blk(256);
     if (po) {
-        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, true>), grd, blk, 0, s, ta);
-        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, false>), grd, blk, 0, s, ta);
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, true, false>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, false, false>), grd, blk, 0, s, ta);
+    } else if (ta.cf.real) {
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, true, true>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false, true>), grd, blk, 0, s, ta);
     } else {
-        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, true>), grd, blk, 0, s, ta);
-        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false>), grd, blk, 0, s, ta);
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, true, false>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false, false>), grd, blk, 0, s, ta);
     }
     return hipGetLastError();
 }
@@ -1131,15 +1188,18 @@ hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *
 template <typename T, int ST, int NPOL>
 static hipError_t degrid_t(const DegridArgs &da, bool po, bool small, hipStream_t s) {
     dim3 blk(256);
+    const bool re = !po && da.cf.real;
     if (small) {
         dim3 grd(nblk(da.n_groups, 16));
-        if (po) hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, true>), grd, blk, 0, s, da);
-        else hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, false>), grd, blk, 0, s, da);
+        if (po) hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, true, false>), grd, blk, 0, s, da);
+        else if (re) hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, false, true>), grd, blk, 0, s, da);
+        else hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, false, false>), grd, blk, 0, s, da);
         return hipGetLastError();
     }
     dim3 grd(nblk(da.n_groups, 4));
-    if (po) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, true>), grd, blk, 0, s, da);
-    else hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false>), grd, blk, 0, s, da);
+    if (po) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, true, false>), grd, blk, 0, s, da);
+    else if (re) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false, true>), grd, blk, 0, s, da);
+    else hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false, false>), grd, blk, 0, s, da);
     return hipGetLastError();
 }
 

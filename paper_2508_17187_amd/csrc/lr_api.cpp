@@ -163,6 +163,10 @@ CFView view_of(const lr_cf *cf) {
     v.n_w = cf->spec.n_w;
     v.n_fg = cf->spec.n_fg;
     v.storage = cf->spec.storage;
+    // the PS taper alone (and the w = 0 plane) transforms to a real, even
+    // kernel: its imaginary parts are rounding noise
+    const uint32_t t = cf->spec.terms;
+    v.real = !(t & LR_TERM_A) && (!(t & LR_TERM_W) || cf->spec.n_w == 1) ? 1 : 0;
     return v;
 }
 

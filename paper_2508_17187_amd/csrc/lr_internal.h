@@ -96,6 +96,7 @@ struct CFView {
     const float *scale;         // [n_fg*n_w] 2^-e (1 for f32 / f64)
     const int32_t *h;           // [n_w]
     int32_t O, n_w, n_fg, storage;
+    int32_t real;               // every value real (no A term, no w-dependence)
 };
 
 }  // namespace lr
