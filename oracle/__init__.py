@@ -16,6 +16,8 @@ Layout
   hogbom       Hogbom minor cycle
   calibration  diagonal G-Jones solve: ratio averages, update direction,
                damped update, exit test
+  mosaic       change of phase centre per field and virtual antennas for
+               the field-shifted kernels
 
 Parity status: every function is pinned by a CPU test against something
 other than itself (closed forms, brute force, library routines, invariants);
