@@ -266,6 +266,30 @@ lr_status lr_image_normalize(const lr_cf *cf, lr_precision precision, const void
                              const double *gcf_x, const double *gcf_y, const double *sumwt,
                              void *out, lr_stream stream);
 
+/* ---- mosaic rows of the imaging-mode table (Eq. CIJ) --------------------- */
+
+/* Change of phase centre of mosaic data, in place: every sample of a row
+ * whose field f is in [0, nfield) is multiplied by
+ *     exp(sign 2 pi i (u l_f + v m_f)),  u = u_m nu / c, v = v_m nu / c,
+ * the argument formed in FP64 and reduced modulo 1; sign = -1 for
+ * direction < 0 (from the field's phase centre s(P) to the joint image
+ * centre s0, before gridding), +1 otherwise (back, after degridding).  The
+ * w-term of the change is not applied (flat-sky shift).  The kernel shift
+ * of a field is the pointing phasor of lr_grid / lr_degrid on virtual
+ * antennas f * nant + a with offsets ant_dlm[a] + field_dlm[f].
+ *   vis        [nrow][nchan][npol] complex128 (LR_F64) or complex64 (LR_F32),
+ *              device, updated in place
+ *   uvw        [nrow][3] metres, device;  freq_hz [nchan] host
+ *   field      [nrow] int32, device (rows outside [0, nfield) unchanged)
+ *   field_dlm  [nfield][2] (l, m) of each field's phase centre relative to
+ *              the image centre, direction cosines, device
+ * LR_E_ARG for NULL pointers or negative sizes, LR_E_DTYPE for other
+ * precisions. */
+lr_status lr_rephase(int64_t nrow, int32_t nchan, int32_t npol, lr_precision precision,
+                     void *vis, const double *uvw, const double *freq_hz, const int32_t *field,
+                     const double *field_dlm, int32_t nfield, int32_t direction,
+                     lr_stream stream);
+
 /* ---- calibration: diagonal G-Jones (the calibration section) -------------- */
 
 /* PreSolvePrep (Eq. VAvg): ratio averages of observed to model visibilities

@@ -587,6 +587,22 @@ lr_status lr_hogbom(const void *psf, void *residual, void *model, int32_t nx, in
     return LR_OK;
 }
 
+lr_status lr_rephase(int64_t nrow, int32_t nchan, int32_t npol, lr_precision precision,
+                     void *vis, const double *uvw, const double *freq_hz, const int32_t *field,
+                     const double *field_dlm, int32_t nfield, int32_t direction,
+                     lr_stream stream) {
+    if (precision != LR_F64 && precision != LR_F32)
+        return fail(LR_E_DTYPE, "visibilities are complex128 (LR_F64) or complex64 (LR_F32)");
+    if (nrow < 0 || nchan < 0 || npol < 1 || nfield < 0)
+        return fail(LR_E_ARG, "negative size");
+    if (nrow == 0 || nchan == 0 || nfield == 0) return LR_OK;
+    if (!vis || !uvw || !freq_hz || !field || !field_dlm) return fail(LR_E_ARG, "NULL argument");
+    hipError_t e = launch_rephase(vis, uvw, freq_hz, field, field_dlm, nrow, nchan, npol, nfield,
+                                  (int)precision, direction, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "rephase");
+    return LR_OK;
+}
+
 lr_status lr_cal_vavg(int64_t nrow, int32_t nchan, int32_t npol, lr_precision precision,
                       const void *vis_obs, const void *vis_model, const void *weight,
                       const int32_t *ant1, const int32_t *ant2, int32_t nant,

@@ -109,4 +109,10 @@ hipError_t launch_cal_solve(const double *X, const double *w, int32_t nant, int6
                             double alpha, double delta, int32_t max_iter, double *g,
                             int32_t *iterations, double *change, hipStream_t s);
 
+// ---- mosaic (k_mosaic.hip) ---------------------------------------------------------
+hipError_t launch_rephase(void *vis, const double *uvw, const double *freq_hz,
+                          const int32_t *field, const double *field_dlm, int64_t nrow,
+                          int32_t nchan, int32_t npol, int32_t nfield, int precision,
+                          int32_t direction, hipStream_t s);
+
 }  // namespace lr

@@ -82,6 +82,9 @@ EXPORTS = {
                            C.c_size_t, C.c_void_p]),
     "lr_debug_map": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p]),
     "lr_gcf": (C.c_int, [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_void_p, C.c_void_p]),
+    "lr_rephase": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int, C.c_void_p, C.c_void_p,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_int32,
+                             C.c_void_p]),
     "lr_cal_vavg": (C.c_int, [C.c_int64, C.c_int32, C.c_int32, C.c_int, C.c_void_p, C.c_void_p,
                               C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                               C.c_int32, C.c_void_p, C.c_int32, C.c_int32, C.c_void_p,
@@ -476,3 +479,18 @@ def lr_cal_solve(X, w, g0=None, alpha=0.5, delta=1e-10, max_iter=500, stream=Non
     _check(lib().lr_cal_solve(_ptr(X.contiguous()), _ptr(w.contiguous()), nant, n, alpha, delta,
                               max_iter, _ptr(g), _ptr(it), _ptr(ch), _stream(stream)))
     return g, it, ch
+
+
+def lr_rephase(vis, uvw, freq_hz, field, field_dlm, to_image_centre=True, stream=None):
+    """Move mosaic visibilities [nrow, nchan, npol] (device, in place) from
+    each row's field phase centre to the joint image centre, or back."""
+    nrow, nchan, npol = vis.shape
+    p = LR_F64 if vis.dtype == torch.complex128 else LR_F32
+    if not vis.is_contiguous() or field.dtype != torch.int32 or field_dlm.dtype != torch.float64:
+        raise LRError(LR_E_DTYPE, "contiguous vis, int32 field ids and float64 offsets expected")
+    freq = np.ascontiguousarray(freq_hz, np.float64)
+    _check(lib().lr_rephase(nrow, nchan, npol, p, _ptr(vis), _ptr(uvw), freq.ctypes.data,
+                            _ptr(field.contiguous()), _ptr(field_dlm.contiguous()),
+                            int(field_dlm.shape[0]), -1 if to_image_centre else 1,
+                            _stream(stream)))
+    return vis
