@@ -356,6 +356,56 @@ def calibration_bench(wl, form, steps):
             "noise_per_sample": 0.01}
 
 
+def mosaic_bench(wl, form, steps):
+    """The W-projection data split into three fields (thirds of the
+    observation in time) whose phase centres lie 60 arcsec from the image
+    centre: the change of phase centre (lr_rephase, in place on a copy) and
+    the mosaic gridding call (pointing phasor on virtual antennas), against
+    the single-pointing gridding call of the same data."""
+    import numpy as np
+    import torch
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import workload as W
+    from paper_2508_17187_amd.mosaic import Mosaic
+    p = lr.PRECISIONS[form]
+    cf = W.build_cf(wl, p)
+    v = W.device_vis(wl, p, pointing=False)
+    nrow = wl.obs.nrow
+    nant = int(max(wl.obs.ant1.max(), wl.obs.ant2.max())) + 1
+    a = 60.0 * np.pi / (180.0 * 3600.0)
+    offs = torch.tensor([[a, 0.0], [-a, 0.5 * a], [0.0, -a]], dtype=torch.float64, device="cuda")
+    field = torch.as_tensor((np.arange(nrow) * 3 // nrow).astype(np.int32), device="cuda")
+    mos = Mosaic(field, offs, torch.as_tensor(wl.obs.ant1.astype(np.int32), device="cuda"),
+                 torch.as_tensor(wl.obs.ant2.astype(np.int32), device="cuda"), nant)
+    moved = v.vis.clone()
+
+    def timed(f, n):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    t_re = timed(lambda: lr.lr_rephase(moved, v.uvw, v.freq, mos.field, mos.field_dlm), steps)
+    vm = mos.vis(v, moved)
+    t0 = time.perf_counter()
+    vm.plan = lr.Plan(cf, vm)
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    g = W.empty_grid(wl, p)
+    wg = lr._work(lr.LR_OP_GRID, cf, vm, p, None)
+    t_grid = timed(lambda: lr.lr_grid_overwrite(cf, vm, p, g, work=wg), steps)
+    info = vm.plan.info()
+    cplx = 16 if p == lr.LR_F64 else 8
+    byts = 2 * nrow * wl.obs.nchan * wl.grid.npol * cplx + nrow * 28
+    return {"form": form, "fields": 3, "field_offset_arcsec": 60.0,
+            "rephase_ms": 1e3 * t_re, "rephase_gb_per_s": byts / t_re / 1e9,
+            "mosaic_grid_call_ms": 1e3 * t_grid, "mosaic_plan_build_ms": 1e3 * t_plan,
+            "mosaic_groups": info["n_groups"], "kept_pairs": info["n_kept"]}
+
+
 def large_image_bench(steps, warmup, ev):
     """The large single image: all 1,293,926,400 samples of the 8 h
     observation streamed from pinned host memory in 13 chunks of 1e8
@@ -665,6 +715,9 @@ def main():
     log("calibration")
     calib = calibration_bench(wl, args.form, args.steps)
     log("  ", json.dumps(calib))
+    log("mosaic")
+    mosaic = mosaic_bench(wl, args.form, args.steps)
+    log("  ", json.dumps(mosaic))
     hbm = None
     if args.ps:
         # the same data through the Standard kernel (PS, S = 7, O = 100, one
@@ -709,6 +762,7 @@ def main():
     out["image"] = images
     out["cf_cache"] = cache
     out["calibration"] = calib
+    out["mosaic"] = mosaic
     if hbm is not None:
         out["hbm_bound_workload"] = hbm
     if args.large:
