@@ -668,7 +668,7 @@ def main():
                     help="run one 1 GiB device copy first (scale of the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would "
+        print("bench.py measures one GPU: there is no multi-GPU path (each GPU would "
               "grid its share of the rows into a private grid, followed by one sum of grids)",
               file=sys.stderr)
         sys.exit(2)

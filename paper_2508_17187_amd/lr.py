@@ -163,7 +163,7 @@ class CF:
             _check(L.lr_cf_build(C.byref(self.spec), C.byref(self.grid), _ptr(self.blob),
                                  nbytes, _ptr(work), wb, _stream(stream),
                                  C.byref(self.handle)))
-            self._work = work      # kept until the build has run on the stream
+            self._work = work      # kept until the CF build has run on the stream
         else:
             self.blob = blob
             _check(L.lr_cf_attach(C.byref(self.spec), C.byref(self.grid), _ptr(blob),
