@@ -406,6 +406,51 @@ def mosaic_bench(wl, form, steps):
             "mosaic_groups": info["n_groups"], "kept_pairs": info["n_kept"]}
 
 
+def deterministic_bench(wl, form, steps):
+    """The gridding call (lr_grid_overwrite with sums of weights) on the
+    W-projection data in the default and in the deterministic order
+    (lr_set_deterministic), and whether two deterministic calls agree bit
+    for bit."""
+    import torch
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import workload as W
+    p = lr.PRECISIONS[form]
+    cf = W.build_cf(wl, p)
+    v = W.device_vis(wl, p)
+    v.plan = lr.Plan(cf, v)
+    g = W.empty_grid(wl, p)
+    sw = torch.zeros((wl.grid.nplane, wl.grid.npol), dtype=torch.float64, device="cuda")
+    wg = lr._work(lr.LR_OP_GRID, cf, v, p, None)
+
+    def call():
+        lr.lr_grid_overwrite(cf, v, p, g, sumwt=sw, work=wg)
+
+    def timed(n):
+        call()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(n):
+            call()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / n
+
+    t_default = timed(steps)
+    prev = lr.set_deterministic(True)
+    try:
+        t_det = timed(steps)
+        call()
+        g1, s1 = g.clone(), sw.clone()
+        call()
+        torch.cuda.synchronize()
+        same = bool(torch.equal(g1.view(torch.uint8), g.view(torch.uint8))
+                    and torch.equal(s1.view(torch.uint8), sw.view(torch.uint8)))
+    finally:
+        lr.set_deterministic(prev)
+    return {"form": form, "grid_call_ms": 1e3 * t_default,
+            "deterministic_grid_call_ms": 1e3 * t_det, "slowdown": t_det / t_default,
+            "repeat_bit_identical": same}
+
+
 def large_image_bench(steps, warmup, ev):
     """The large single image: all 1,293,926,400 samples of the 8 h
     observation streamed from pinned host memory in 13 chunks of 1e8
@@ -718,6 +763,9 @@ def main():
     log("mosaic")
     mosaic = mosaic_bench(wl, args.form, args.steps)
     log("  ", json.dumps(mosaic))
+    log("deterministic order")
+    determ = deterministic_bench(wl, args.form, args.steps)
+    log("  ", json.dumps(determ))
     hbm = None
     if args.ps:
         # the same data through the Standard kernel (PS, S = 7, O = 100, one
@@ -763,6 +811,7 @@ def main():
     out["cf_cache"] = cache
     out["calibration"] = calib
     out["mosaic"] = mosaic
+    out["deterministic"] = determ
     if hbm is not None:
         out["hbm_bound_workload"] = hbm
     if args.large:

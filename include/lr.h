@@ -199,6 +199,19 @@ void lr_plan_free(lr_plan *plan);
 lr_status lr_plan_info(const lr_plan *plan, int64_t *n_groups, int64_t *n_kept,
                        int64_t *n_pairs, int64_t *taps);
 
+/* Deterministic order, process-wide (default off): with on != 0 every later
+ * lr_grid, lr_grid_overwrite and lr_sumwt call forms its sums in an order
+ * that does not depend on scheduling, so that repeated calls on the same
+ * inputs (alone or beside other work on the device) give bit-identical
+ * grids and sums of weights: group sums one group at a time in the plan's
+ * sorted order, sums of weights from fixed per-(channel, row block)
+ * partials added in channel order, and one workgroup per grid tile instead
+ * of atomic flushes of tiles shared by several chunks.  Slower; the results
+ * equal the default mode's up to FP rounding order.  lr_make_psf keeps its
+ * atomic mirror adds.  lr_deterministic returns the current setting. */
+lr_status lr_set_deterministic(int32_t on);
+int32_t lr_deterministic(void);
+
 /* Diagnostic timing hook: the next lr_grid / lr_make_psf / lr_degrid on the
  * calling thread records `start` (a hipEvent_t) on its stream just before
  * its main kernel (the gridder or the degridder) and `stop` just after it,

@@ -634,7 +634,7 @@ constexpr int kWaitVm0 = 0x0F70;
 // items of a chunk as ballot bits, 64 per word
 constexpr int kMaskWords = (kChunkMax + 63) / 64;
 
-template <typename T, int ST, int NPOL, bool PO, bool PSF, bool RE>
+template <typename T, int ST, int NPOL, bool PO, bool PSF, bool RE, bool DET>
 __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     constexpr int B = kItemBatch;
     constexpr int E = CFRaw<ST>::bytes;
@@ -642,17 +642,18 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     __shared__ TileItem items[kChunkMax];
     __shared__ cpx<T> avs[kChunkMax * NPOL];
     __shared__ GroupMeta gms[PO ? kChunkMax : 1];
-    const int c = blockIdx.x;
-    if (!PSF && c >= a.n_chunks) {      // GRID_SET: tiles without pairs
-        const int tile = c - a.n_chunks;
+    const int c0 = blockIdx.x;
+    if (!PSF && c0 >= a.n_chunks) {      // GRID_SET: tiles without pairs
+        const int tile = c0 - a.n_chunks;
         if (a.tile_state[tile] == 0)
             clear_tile<T, NPOL>(tile, a.ntx, a.nty, a.nx, a.ny, a.pol_stride, (cpx<T> *)a.grid);
         return;
     }
-    const int32_t s0 = a.chunk_start[c];
-    const int n = a.chunk_start[c + 1] - s0;
-    const int32_t key = a.chunk_tile[c];
-    const bool excl = !PSF && a.chunk_excl[c];
+    const int32_t key = a.chunk_tile[c0];
+    // DET (deterministic order): the workgroup of a tile's first chunk takes
+    // all of the tile's chunks in order and owns the tile; the others exit
+    if (DET && c0 > 0 && a.chunk_tile[c0 - 1] == key) return;
+    const bool excl = !PSF && (DET || a.chunk_excl[c0]);
     const int tx = key % a.ntx;
     const int rest = key / a.ntx;
     const int ty = rest % a.nty;
@@ -664,113 +665,119 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     const int yb = ty * kTile + 4 * (threadIdx.x >> 5);
     const int band0 = ty * kTile + 8 * (threadIdx.x >> 6);
     const cpx<T> *Av = (const cpx<T> *)a.A;
-    for (int t = threadIdx.x; t < n; t += blockDim.x) {
-        const int32_t g = a.tp_group[s0 + t];
-        const GroupMeta gm = a.groups[g];
-        const int h = gm.h;
-        TileItem ti;
-        ti.cf_off = gm.cf_off;
-        ti.bx = gm.pu - h;
-        ti.by = gm.pv - h;
-        ti.S = 2 * h + 1;
-        ti.conj = gm.conj;
-        ti.sc = gm.sc;
-        ti.h = h;
-        items[t] = ti;
-        for (int p = 0; p < NPOL; ++p) avs[t * NPOL + p] = Av[(int64_t)g * NPOL + p];
-        if (PO) gms[t] = gm;
-    }
-    __syncthreads();
-    // lane i tests item i against the wavefront's band: the ballot lists the
-    // items this wavefront works on (wave-uniform)
-    uint64_t todo[kMaskWords];
-    for (int w = 0; w < kMaskWords; ++w) {
-        bool hit = false;
-        const int it = w * 64 + lane;
-        if (it < n) {
-            const TileItem ti = items[it];
-            hit = ti.by < band0 + 8 && ti.by + ti.S > band0;
-        }
-        todo[w] = __ballot(hit);
-    }
-    auto pending = [&]() {
-        uint64_t any = 0;
-        for (int w = 0; w < kMaskWords; ++w) any |= todo[w];
-        return any != 0;
-    };
-    auto next = [&]() {
-        for (int w = 0; w < kMaskWords; ++w)
-            if (todo[w]) {
-                const int i = __builtin_ctzll(todo[w]);
-                todo[w] &= todo[w] - 1;
-                return w * 64 + i;
-            }
-        return -1;
-    };
     cpx<T> acc[4][NPOL];
     for (int j = 0; j < 4; ++j)
         for (int p = 0; p < NPOL; ++p) acc[j][p] = {(T)0, (T)0};
     const char *table = (const char *)a.cf.table;
-    while (pending()) {
-        int idx[B];
-        for (int b = 0; b < B; ++b) idx[b] = next();
-        Raw cv[B][4];
-        bool ok[B][4];
-        int dxs[B], rs[B];
-        float scs[B];
-        // the kernel loads of the whole batch are issued before any is used;
-        // an item's fields are wave-uniform, so its sub-kernel base address
-        // is scalar and a lane only adds its 32-bit offset; cells outside
-        // the footprint neither load nor accumulate
-        for (int b = 0; b < B; ++b) {
-            for (int j = 0; j < 4; ++j) ok[b][j] = false;
-            dxs[b] = rs[b] = 0;
-            if (idx[b] < 0) continue;
-            const TileItem ti = items[idx[b]];
-            const int S = uni(ti.S);
-            const char *base = table + uni64(ti.cf_off) * E;
-            scs[b] = ti.sc;
-            const int dx = x - uni(ti.bx);
-            const int r = yb - uni(ti.by);
-            dxs[b] = dx;
-            rs[b] = r;
-            const bool cin = (unsigned)dx < (unsigned)S;
-            const unsigned SS = (unsigned)(S * S);
-            int off = __mul24(r, S) + dx;  // element offset of the lane's first row
-            for (int j = 0; j < 4; ++j, off += S) {
-                ok[b][j] = cin && (unsigned)off < SS;
-                if (ok[b][j]) cv[b][j] = *(const Raw *)(base + (uint32_t)off * (uint32_t)E);
-            }
+    for (int c = c0;;) {
+        const int32_t s0 = a.chunk_start[c];
+        const int n = a.chunk_start[c + 1] - s0;
+        for (int t = threadIdx.x; t < n; t += blockDim.x) {
+            const int32_t g = a.tp_group[s0 + t];
+            const GroupMeta gm = a.groups[g];
+            const int h = gm.h;
+            TileItem ti;
+            ti.cf_off = gm.cf_off;
+            ti.bx = gm.pu - h;
+            ti.by = gm.pv - h;
+            ti.S = 2 * h + 1;
+            ti.conj = gm.conj;
+            ti.sc = gm.sc;
+            ti.h = h;
+            items[t] = ti;
+            for (int p = 0; p < NPOL; ++p) avs[t * NPOL + p] = Av[(int64_t)g * NPOL + p];
+            if (PO) gms[t] = gm;
         }
-        for (int b = 0; b < B; ++b) {
-            if (idx[b] < 0) continue;
-            const int t = idx[b];
-            const bool cj = uni(items[t].conj) != 0;
-            cpx<T> av[NPOL];
-            for (int p = 0; p < NPOL; ++p) av[p] = avs[t * NPOL + p];
-            for (int j = 0; j < 4; ++j) {
-                if (!ok[b][j]) continue;
-                if constexpr (RE) {
-                    const T c = CFReal<ST>::decode(cv[b][j], scs[b]);
-                    for (int p = 0; p < NPOL; ++p) {
-                        acc[j][p].x = fma(c, av[p].x, acc[j][p].x);
-                        acc[j][p].y = fma(c, av[p].y, acc[j][p].y);
-                    }
-                } else {
-                    cpx<T> cw = CFRaw<ST>::decode(cv[b][j], scs[b]);
-                    if (cj) cw.y = -cw.y;
-                    if (PO) {
-                        const int h = items[t].h;
-                        cw = cmul(cw, phasor<T>(gms[t], dxs[b] - h, rs[b] + j - h, a.cf.O));
-                    }
-                    for (int p = 0; p < NPOL; ++p) cmac(acc[j][p], cw, av[p]);
+        __syncthreads();
+        // lane i tests item i against the wavefront's band: the ballot lists the
+        // items this wavefront works on (wave-uniform)
+        uint64_t todo[kMaskWords];
+        for (int w = 0; w < kMaskWords; ++w) {
+            bool hit = false;
+            const int it = w * 64 + lane;
+            if (it < n) {
+                const TileItem ti = items[it];
+                hit = ti.by < band0 + 8 && ti.by + ti.S > band0;
+            }
+            todo[w] = __ballot(hit);
+        }
+        auto pending = [&]() {
+            uint64_t any = 0;
+            for (int w = 0; w < kMaskWords; ++w) any |= todo[w];
+            return any != 0;
+        };
+        auto next = [&]() {
+            for (int w = 0; w < kMaskWords; ++w)
+                if (todo[w]) {
+                    const int i = __builtin_ctzll(todo[w]);
+                    todo[w] &= todo[w] - 1;
+                    return w * 64 + i;
+                }
+            return -1;
+        };
+        while (pending()) {
+            int idx[B];
+            for (int b = 0; b < B; ++b) idx[b] = next();
+            Raw cv[B][4];
+            bool ok[B][4];
+            int dxs[B], rs[B];
+            float scs[B];
+            // the kernel loads of the whole batch are issued before any is used;
+            // an item's fields are wave-uniform, so its sub-kernel base address
+            // is scalar and a lane only adds its 32-bit offset; cells outside
+            // the footprint neither load nor accumulate
+            for (int b = 0; b < B; ++b) {
+                for (int j = 0; j < 4; ++j) ok[b][j] = false;
+                dxs[b] = rs[b] = 0;
+                if (idx[b] < 0) continue;
+                const TileItem ti = items[idx[b]];
+                const int S = uni(ti.S);
+                const char *base = table + uni64(ti.cf_off) * E;
+                scs[b] = ti.sc;
+                const int dx = x - uni(ti.bx);
+                const int r = yb - uni(ti.by);
+                dxs[b] = dx;
+                rs[b] = r;
+                const bool cin = (unsigned)dx < (unsigned)S;
+                const unsigned SS = (unsigned)(S * S);
+                int off = __mul24(r, S) + dx;  // element offset of the lane's first row
+                for (int j = 0; j < 4; ++j, off += S) {
+                    ok[b][j] = cin && (unsigned)off < SS;
+                    if (ok[b][j]) cv[b][j] = *(const Raw *)(base + (uint32_t)off * (uint32_t)E);
                 }
             }
+            for (int b = 0; b < B; ++b) {
+                if (idx[b] < 0) continue;
+                const int t = idx[b];
+                const bool cj = uni(items[t].conj) != 0;
+                cpx<T> av[NPOL];
+                for (int p = 0; p < NPOL; ++p) av[p] = avs[t * NPOL + p];
+                for (int j = 0; j < 4; ++j) {
+                    if (!ok[b][j]) continue;
+                    if constexpr (RE) {
+                        const T c = CFReal<ST>::decode(cv[b][j], scs[b]);
+                        for (int p = 0; p < NPOL; ++p) {
+                            acc[j][p].x = fma(c, av[p].x, acc[j][p].x);
+                            acc[j][p].y = fma(c, av[p].y, acc[j][p].y);
+                        }
+                    } else {
+                        cpx<T> cw = CFRaw<ST>::decode(cv[b][j], scs[b]);
+                        if (cj) cw.y = -cw.y;
+                        if (PO) {
+                            const int h = items[t].h;
+                            cw = cmul(cw, phasor<T>(gms[t], dxs[b] - h, rs[b] + j - h, a.cf.O));
+                        }
+                        for (int p = 0; p < NPOL; ++p) cmac(acc[j][p], cw, av[p]);
+                    }
+                }
+            }
+            // every load of the batch has landed (rows that no lane needed were
+            // skipped): saying so lets the next batch reuse their registers
+            // without a wait in front of each load
+            __builtin_amdgcn_s_waitcnt(kWaitVm0);
         }
-        // every load of the batch has landed (rows that no lane needed were
-        // skipped): saying so lets the next batch reuse their registers
-        // without a wait in front of each load
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
+        if (!DET || ++c >= a.n_chunks || a.chunk_tile[c] != key) break;
+        __syncthreads();      // every wavefront is done with this chunk's items
     }
     T *grid = (T *)a.grid;
     const bool set = excl && a.set;
@@ -1034,6 +1041,79 @@ __global__ __launch_bounds__(256) void k_expand(int64_t n_pairs, const int32_t *
 }
 
 // ---------------------------------------------------------------------------
+// Deterministic mode: sums whose order does not depend on scheduling.
+// Group sums: one thread per group adds its members' W V in the plan's
+// sorted order and stores the result.
+template <typename T, int NPOL, bool UNIT>
+__global__ __launch_bounds__(256) void k_presum_det(int64_t n_groups, const int32_t *group_start,
+                                                    const int32_t *order, const T *vis,
+                                                    const T *weight, cpx<T> *A) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    cpx<T> a[NPOL];
+    for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
+    for (int32_t i = group_start[g]; i < group_start[g + 1]; ++i) {
+        const int64_t pair = order[i];
+        for (int p = 0; p < NPOL; ++p) {
+            const T W = weight ? weight[pair * NPOL + p] : (T)1;
+            if (W == (T)0) continue;
+            if (UNIT) {
+                a[p].x += W;
+            } else {
+                const T *v = vis + 2 * (pair * NPOL + p);
+                a[p].x += W * v[0];
+                a[p].y += W * v[1];
+            }
+        }
+    }
+    for (int p = 0; p < NPOL; ++p) A[g * NPOL + p] = a[p];
+}
+
+// Sums of weights: block (c, k) adds the kept weights of channel c over
+// rows k * 256 + t + i * 256 * kDetRowBlocks, then a fixed tree over its
+// threads writes part[c][k][pol]; one thread per (plane, pol) adds the
+// partials of the plane's channels in channel and block order.
+template <typename T, int NPOL>
+__global__ __launch_bounds__(256) void k_sumwt_part(int64_t nrow, int32_t nchan,
+                                                    const int32_t *pair_group, const T *weight,
+                                                    double *part) {
+    __shared__ double red[256][NPOL];
+    const int c = blockIdx.x / kDetRowBlocks, k = blockIdx.x % kDetRowBlocks;
+    double s[NPOL];
+    for (int p = 0; p < NPOL; ++p) s[p] = 0.0;
+    for (int64_t r = (int64_t)k * 256 + threadIdx.x; r < nrow; r += 256 * kDetRowBlocks) {
+        const int64_t j = r * nchan + c;
+        if (pair_group[j] < 0) continue;          // dropped or skipped
+        for (int p = 0; p < NPOL; ++p) {
+            const T W = weight ? weight[j * NPOL + p] : (T)1;
+            if (W != (T)0) s[p] += (double)W;
+        }
+    }
+    for (int p = 0; p < NPOL; ++p) red[threadIdx.x][p] = s[p];
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off)
+            for (int p = 0; p < NPOL; ++p) red[threadIdx.x][p] += red[threadIdx.x + off][p];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        for (int p = 0; p < NPOL; ++p) part[((int64_t)c * kDetRowBlocks + k) * NPOL + p] = red[0][p];
+}
+
+__global__ void k_sumwt_finish(int32_t nchan, const ChanConst *cc, const double *part,
+                               int32_t nplane, int32_t npol, double *sumwt) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nplane * npol) return;
+    const int plane = t / npol, p = t % npol;
+    double s = 0.0;
+    for (int c = 0; c < nchan; ++c) {
+        if (cc[c].plane != plane) continue;
+        for (int k = 0; k < kDetRowBlocks; ++k) s += part[((int64_t)c * kDetRowBlocks + k) * npol + p];
+    }
+    sumwt[t] += s;
+}
+
+// ---------------------------------------------------------------------------
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 template <typename T, int NPOL>
@@ -1102,35 +1182,40 @@ hipError_t launch_counts(const lr_plan *P, const void *weight, int precision, in
 }
 
 template <typename T, int ST, int NPOL>
-static hipError_t grid_t(const TileArgs &ta, int64_t n_blocks, bool po, bool psf,
+static hipError_t grid_t(const TileArgs &ta, int64_t n_blocks, bool po, bool psf, bool det,
                          hipStream_t s) {
     dim3 grd((unsigned)n_blocks), blk(256);
+    // the point-spread function's mirror image is always flushed with
+    // atomics: it has no deterministic form
     if (po) {
-        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, true, false>), grd, blk, 0, s, ta);
-        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, false, false>), grd, blk, 0, s, ta);
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, true, false, false>), grd, blk, 0, s, ta);
+        else if (det) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, false, false, true>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, true, false, false, false>), grd, blk, 0, s, ta);
     } else if (ta.cf.real) {
-        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, true, true>), grd, blk, 0, s, ta);
-        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false, true>), grd, blk, 0, s, ta);
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, true, true, false>), grd, blk, 0, s, ta);
+        else if (det) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false, true, true>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false, true, false>), grd, blk, 0, s, ta);
     } else {
-        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, true, false>), grd, blk, 0, s, ta);
-        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false, false>), grd, blk, 0, s, ta);
+        if (psf) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, true, false, false>), grd, blk, 0, s, ta);
+        else if (det) hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false, false, true>), grd, blk, 0, s, ta);
+        else hipLaunchKernelGGL((k_grid_tile<T, ST, NPOL, false, false, false, false>), grd, blk, 0, s, ta);
     }
     return hipGetLastError();
 }
 
 template <typename T, int ST>
 static hipError_t grid_np(const TileArgs &ta, int64_t n_blocks, int npol, bool po, bool psf,
-                          hipStream_t s) {
+                          bool det, hipStream_t s) {
     switch (npol) {
-        case 1: return grid_t<T, ST, 1>(ta, n_blocks, po, psf, s);
-        case 2: return grid_t<T, ST, 2>(ta, n_blocks, po, psf, s);
-        default: return grid_t<T, ST, 4>(ta, n_blocks, po, psf, s);
+        case 1: return grid_t<T, ST, 1>(ta, n_blocks, po, psf, det, s);
+        case 2: return grid_t<T, ST, 2>(ta, n_blocks, po, psf, det, s);
+        default: return grid_t<T, ST, 4>(ta, n_blocks, po, psf, det, s);
     }
 }
 
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
                        int precision, int32_t npol, int32_t nx, int32_t ny, int32_t mode,
-                       hipStream_t s) {
+                       bool det, hipStream_t s) {
     const bool set = mode == GRID_SET;
     // GRID_SET: one more workgroup per tile clears the tiles without pairs
     const int64_t nc = P->n_chunks + (set ? P->n_tiles : 0);
@@ -1141,11 +1226,12 @@ hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *
                 set ? 1 : 0};
     bool po = P->po != 0;
     bool psf = mode == GRID_PSF;
+    det = det && !psf;
     switch (precision) {
-        case LR_F64: return grid_np<double, LR_F64>(ta, nc, npol, po, psf, s);
-        case LR_F32: return grid_np<float, LR_F32>(ta, nc, npol, po, psf, s);
-        case LR_F32_CF16: return grid_np<float, LR_F32_CF16>(ta, nc, npol, po, psf, s);
-        default: return grid_np<float, LR_F32_CFBF16>(ta, nc, npol, po, psf, s);
+        case LR_F64: return grid_np<double, LR_F64>(ta, nc, npol, po, psf, det, s);
+        case LR_F32: return grid_np<float, LR_F32>(ta, nc, npol, po, psf, det, s);
+        case LR_F32_CF16: return grid_np<float, LR_F32_CF16>(ta, nc, npol, po, psf, det, s);
+        default: return grid_np<float, LR_F32_CFBF16>(ta, nc, npol, po, psf, det, s);
     }
 }
 
@@ -1256,6 +1342,53 @@ hipError_t launch_expand(const lr_plan *P, const void *Vg, void *vis, const void
     if (P->n_pairs == 0) return hipSuccess;
     if (precision == LR_F64) return expand_t<double>(P, Vg, vis, weight, npol, s);
     return expand_t<float>(P, Vg, vis, weight, npol, s);
+}
+
+template <typename T, int NPOL>
+static hipError_t presum_det_t(const lr_plan *P, const VisArgs &v, void *A, hipStream_t s) {
+    dim3 grd(nblk(P->n_groups, 256)), blk(256);
+    const T *vis = (const T *)v.vis;
+    const T *wt = (const T *)v.weight;
+    if (v.unit_vis)
+        hipLaunchKernelGGL((k_presum_det<T, NPOL, true>), grd, blk, 0, s, P->n_groups,
+                           P->group_start, P->order, vis, wt, (cpx<T> *)A);
+    else
+        hipLaunchKernelGGL((k_presum_det<T, NPOL, false>), grd, blk, 0, s, P->n_groups,
+                           P->group_start, P->order, vis, wt, (cpx<T> *)A);
+    return hipGetLastError();
+}
+
+hipError_t launch_presum_det(const lr_plan *P, const VisArgs &v, int precision, void *A,
+                             hipStream_t s) {
+    if (P->n_groups == 0) return hipSuccess;
+    const bool f64 = precision == LR_F64;
+    switch (v.npol) {
+        case 1: return f64 ? presum_det_t<double, 1>(P, v, A, s) : presum_det_t<float, 1>(P, v, A, s);
+        case 2: return f64 ? presum_det_t<double, 2>(P, v, A, s) : presum_det_t<float, 2>(P, v, A, s);
+        default: return f64 ? presum_det_t<double, 4>(P, v, A, s) : presum_det_t<float, 4>(P, v, A, s);
+    }
+}
+
+template <typename T, int NPOL>
+static void sumwt_part_t(const lr_plan *P, const void *weight, double *part, hipStream_t s) {
+    hipLaunchKernelGGL((k_sumwt_part<T, NPOL>), dim3((unsigned)(P->nchan * kDetRowBlocks)),
+                       dim3(256), 0, s, P->nrow, P->nchan, P->pair_group, (const T *)weight,
+                       part);
+}
+
+hipError_t launch_sumwt_det(const lr_plan *P, const void *weight, int precision, int32_t npol,
+                            int32_t nplane, double *part, double *sumwt, hipStream_t s) {
+    if (P->n_pairs == 0 || !sumwt) return hipSuccess;
+    const bool f64 = precision == LR_F64;
+    switch (npol) {
+        case 1: f64 ? sumwt_part_t<double, 1>(P, weight, part, s) : sumwt_part_t<float, 1>(P, weight, part, s); break;
+        case 2: f64 ? sumwt_part_t<double, 2>(P, weight, part, s) : sumwt_part_t<float, 2>(P, weight, part, s); break;
+        default: f64 ? sumwt_part_t<double, 4>(P, weight, part, s) : sumwt_part_t<float, 4>(P, weight, part, s);
+    }
+    const int n = nplane * npol;
+    hipLaunchKernelGGL(k_sumwt_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                       P->nchan, P->cc, part, nplane, npol, sumwt);
+    return hipGetLastError();
 }
 
 }  // namespace lr

@@ -485,6 +485,7 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->n_tiles = tile_count(g.nx, g.ny, g.nplane);
     P->shared_tiles = (int32_t *)(buf + L.shared_tiles);
     P->n_shared = 0;
+    P->cc = d_cc;
     P->n_kept = P->n_groups = P->n_tile_pairs = P->n_chunks = P->taps = 0;
     if ((e = launch_zero(P->tile_state, sizeof(int32_t) * P->n_tiles, s)) != hipSuccess)
         return e;

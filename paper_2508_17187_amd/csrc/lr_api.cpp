@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <new>
@@ -22,6 +23,8 @@ namespace {
 
 thread_local std::string g_err;
 thread_local hipEvent_t g_prof_start = nullptr, g_prof_stop = nullptr;
+// deterministic gridding sums (lr_set_deterministic), process-wide
+std::atomic<int> g_det{0};
 
 // Record the pending profile events around the main kernel of a call.
 struct ProfileScope {
@@ -363,6 +366,11 @@ lr_status build_plan(const lr_cf *cf, const lr_vis *v, int psf, void *buf, size_
     return LR_OK;
 }
 
+// Workspace of the deterministic sums of weights.
+static size_t det_bytes(int32_t nchan, int32_t npol) {
+    return al256((size_t)std::max(nchan, 1) * kDetRowBlocks * npol * sizeof(double));
+}
+
 // Resolve the plan of a call: the caller's, or a transient one at the start
 // of the workspace.  Returns the workspace bytes it used.
 lr_status resolve_plan(const lr_cf *cf, const lr_vis *v, int psf, void *work,
@@ -426,6 +434,8 @@ size_t lr_workspace_bytes(int op, const lr_cf_spec *spec, const lr_grid_spec *gr
     size_t per = 0;
     if (op == LR_OP_GRID || op == LR_OP_PSF || op == LR_OP_DEGRID)
         per = al256((size_t)std::max<int64_t>(n_groups, 1) * grid->npol * cplx_bytes(precision));
+    // partial sums of weights of the deterministic mode
+    if (op == LR_OP_GRID || op == LR_OP_SUMWT) per += det_bytes(vis->nchan, grid->npol);
     return plan + per + 256;
 }
 
@@ -652,6 +662,13 @@ lr_status lr_plan_info(const lr_plan *plan, int64_t *n_groups, int64_t *n_kept,
     return LR_OK;
 }
 
+lr_status lr_set_deterministic(int32_t on) {
+    g_det.store(on ? 1 : 0);
+    return LR_OK;
+}
+
+int32_t lr_deterministic(void) { return g_det.load(); }
+
 lr_status lr_set_profile_events(void *start, void *stop) {
     if ((start == nullptr) != (stop == nullptr))
         return fail(LR_E_ARG, "give both events or neither");
@@ -674,8 +691,12 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
     int64_t ng_bound = vis->plan ? vis->plan->n_groups : (int64_t)vis->nrow * vis->nchan;
     size_t a_bytes = al256((size_t)std::max<int64_t>(ng_bound, 1) * vis->npol * cplx_bytes(precision));
     size_t plan_need = vis->plan ? 0 : al256(plan_total(cf, vis));
-    if (work_bytes < plan_need + a_bytes)
-        return fail(LR_E_WORKSPACE, "workspace needs %zu bytes, got %zu", plan_need + a_bytes, work_bytes);
+    // deterministic order (lr_set_deterministic): not for the PSF
+    const bool det = g_det.load() != 0 && !psf;
+    const size_t d_bytes = det ? det_bytes(vis->nchan, vis->npol) : 0;
+    if (work_bytes < plan_need + a_bytes + d_bytes)
+        return fail(LR_E_WORKSPACE, "workspace needs %zu bytes, got %zu",
+                    plan_need + a_bytes + d_bytes, work_bytes);
     lr_plan tmp;
     const lr_plan *P = nullptr;
     size_t used = 0;
@@ -686,6 +707,30 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
     // group sums start at zero; GRID_SET replaces the outputs, so it also
     // clears sumwt, the counters and the shared tiles
     const bool set = mode == GRID_SET;
+    if (det) {
+        // every sum in a fixed order: group sums stored per group, sums of
+        // weights from fixed partials, one workgroup per tile
+        double *part = (double *)((char *)A + a_bytes);
+        hipError_t e = launch_grid_setup(P, nullptr, 0, set ? sumwt : nullptr,
+                                         sizeof(double) * cf->grid.nplane * vis->npol,
+                                         set ? counters : nullptr, grid, precision, vis->npol,
+                                         cf->grid.nx, cf->grid.ny, set, s);
+        if (e == hipSuccess && counters)
+            e = launch_counts(P, vis->weight, precision, vis->npol, nullptr, counters,
+                              cf->grid.nplane, s);
+        if (e == hipSuccess && sumwt)
+            e = launch_sumwt_det(P, vis->weight, precision, vis->npol, cf->grid.nplane, part,
+                                 sumwt, s);
+        if (e == hipSuccess) e = launch_presum_det(P, va, precision, A, s);
+        if (e == hipSuccess) {
+            prof.begin();
+            e = launch_grid(P, view_of(cf), A, grid, precision, vis->npol, cf->grid.nx,
+                            cf->grid.ny, mode, true, s);
+            prof.end();
+        }
+        if (e != hipSuccess) return dev_fail(e, "grid");
+        return LR_OK;
+    }
     hipError_t e = launch_grid_setup(
         P, A, (size_t)P->n_groups * vis->npol * cplx_bytes(precision), set ? sumwt : nullptr,
         sizeof(double) * cf->grid.nplane * vis->npol, set ? counters : nullptr, grid, precision,
@@ -695,7 +740,7 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
     if (e == hipSuccess) {
         prof.begin();
         e = launch_grid(P, view_of(cf), A, grid, precision, vis->npol, cf->grid.nx,
-                        cf->grid.ny, mode, s);
+                        cf->grid.ny, mode, false, s);
         prof.end();
     }
     if (e != hipSuccess) return dev_fail(e, psf ? "psf" : "grid");
@@ -763,8 +808,15 @@ lr_status lr_sumwt(const lr_cf *cf, const lr_vis *vis, lr_precision precision, d
     const lr_plan *P = nullptr;
     size_t used = 0;
     if ((st = resolve_plan(cf, vis, 0, work, work_bytes, s, tmp, P, used)) != LR_OK) return st;
-    hipError_t e = launch_counts(P, vis->weight, precision, vis->npol, sumwt, counters,
-                                 cf->grid.nplane, s);
+    const bool det = g_det.load() != 0;
+    if (det && work_bytes < used + det_bytes(vis->nchan, vis->npol))
+        return fail(LR_E_WORKSPACE, "workspace needs %zu bytes, got %zu",
+                    used + det_bytes(vis->nchan, vis->npol), work_bytes);
+    hipError_t e = launch_counts(P, vis->weight, precision, vis->npol, det ? nullptr : sumwt,
+                                 counters, cf->grid.nplane, s);
+    if (e == hipSuccess && det && sumwt)
+        e = launch_sumwt_det(P, vis->weight, precision, vis->npol, cf->grid.nplane,
+                             (double *)((char *)work + used), sumwt, s);
     if (e != hipSuccess) return dev_fail(e, "sumwt");
     return LR_OK;
 }

@@ -146,5 +146,6 @@ struct lr_plan {
     int64_t n_tiles;           // nplane * nty * ntx
     int32_t *shared_tiles;     // [n_shared] ids of the tiles in state 2
     int64_t n_shared;
+    const lr::ChanConst *cc;   // [nchan] channel constants (plane of each channel)
     size_t bytes_used;
 };

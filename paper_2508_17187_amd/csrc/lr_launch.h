@@ -64,9 +64,11 @@ hipError_t launch_counts(const lr_plan *P, const void *weight, int precision, in
 // mode: GRID_ADD (grid +=), GRID_PSF (grid += half the mirror pair), GRID_SET
 // (grid =, every cell written; zero_tiles must have run on the same stream)
 enum { GRID_ADD = 0, GRID_PSF = 1, GRID_SET = 2 };
+// det: deterministic order (one workgroup per tile, no atomic flushes; not
+// for GRID_PSF)
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
                        int precision, int32_t npol, int32_t nx, int32_t ny, int32_t mode,
-                       hipStream_t s);
+                       bool det, hipStream_t s);
 // Set-up of a gridding call, one launch: zero the group sums A (a_bytes)
 // and, when given, sumwt and counters; under GRID_SET also the tiles that
 // several chunks share (they are then added to atomically).
@@ -114,5 +116,16 @@ hipError_t launch_rephase(void *vis, const double *uvw, const double *freq_hz,
                           const int32_t *field, const double *field_dlm, int64_t nrow,
                           int32_t nchan, int32_t npol, int32_t nfield, int precision,
                           int32_t direction, hipStream_t s);
+
+// ---- deterministic gridding sums (k_grid.hip) ---------------------------------
+// Row blocks per channel of the deterministic sums of weights; the partials
+// take nchan * kDetRowBlocks * npol doubles of workspace.
+constexpr int kDetRowBlocks = 64;
+// Group sums in the plan's sorted order, stored (no clear needed).
+hipError_t launch_presum_det(const lr_plan *P, const VisArgs &v, int precision, void *A,
+                             hipStream_t s);
+// sumwt[plane][pol] += sum of kept weights, in a fixed order.
+hipError_t launch_sumwt_det(const lr_plan *P, const void *weight, int precision, int32_t npol,
+                            int32_t nplane, double *part, double *sumwt, hipStream_t s);
 
 }  // namespace lr

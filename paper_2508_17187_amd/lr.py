@@ -70,6 +70,8 @@ EXPORTS = {
     "lr_plan_free": (None, [C.c_void_p]),
     "lr_plan_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lr_set_profile_events": (C.c_int, [C.c_void_p, C.c_void_p]),
+    "lr_set_deterministic": (C.c_int, [C.c_int32]),
+    "lr_deterministic": (C.c_int32, []),
     "lr_grid": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                           C.c_void_p, C.c_size_t, C.c_void_p]),
     "lr_grid_overwrite": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
@@ -494,3 +496,11 @@ def lr_rephase(vis, uvw, freq_hz, field, field_dlm, to_image_centre=True, stream
                             int(field_dlm.shape[0]), -1 if to_image_centre else 1,
                             _stream(stream)))
     return vis
+
+
+def set_deterministic(on=True):
+    """Scheduling-independent sums in lr_grid / lr_grid_overwrite / lr_sumwt
+    (lr_set_deterministic); returns the previous setting."""
+    prev = bool(lib().lr_deterministic())
+    _check(lib().lr_set_deterministic(1 if on else 0))
+    return prev
