@@ -393,13 +393,16 @@ __global__ __launch_bounds__(256) void k_presum(
 // A finished run is added to A with an atomic, or simply stored when it is
 // a whole group: a single-run group (kSingleRun) whose run neither began
 // before this wavefront's first step nor continues past its last one.
+// DET (deterministic order) stores those groups and sets done[g], and adds
+// nothing with atomics: the other groups are summed again afterwards, one
+// group at a time, by k_presum_det.
 constexpr int kColW = 8, kColT = 8, kColBlocks = 16;
 
-template <typename T, int NPOL, bool UNIT, bool SUMS>
+template <typename T, int NPOL, bool UNIT, bool SUMS, bool DET>
 __global__ __launch_bounds__(256) void k_presum_col(
     int64_t n_pairs, int64_t L, int64_t ncb, const int32_t *pair_group,
     const GroupMeta *groups, const T *vis, const T *weight, cpx<T> *A, double *sumwt,
-    long long *counters) {
+    long long *counters, uint8_t *done) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
     const int cl = lane & (kColW - 1), tl = lane / kColW;
@@ -421,6 +424,10 @@ __global__ __launch_bounds__(256) void k_presum_col(
     // begun in the previous wavefront: it is never stored, only added
     bool open0 = false;
     auto emit = [&](int g, bool store, const cpx<T> *v) {
+        if (DET) {
+            if (!store) return;
+            done[g] = 1;
+        }
         for (int p = 0; p < NPOL; ++p) {
             if (store) {
                 A[(int64_t)g * NPOL + p] = v[p];
@@ -1042,17 +1049,28 @@ __global__ __launch_bounds__(256) void k_expand(int64_t n_pairs, const int32_t *
 
 // ---------------------------------------------------------------------------
 // Deterministic mode: sums whose order does not depend on scheduling.
-// Group sums: one thread per group adds its members' W V in the plan's
-// sorted order and stores the result.
+// Group sums, stored: lane i of a wavefront owns group 64 w + i.  A group
+// of at most kDetSerial members is added by its lane, one member at a time
+// in the plan's sorted order; a larger one by the whole wavefront, lane l
+// taking members l, l + 64, ... in order, then a fixed shuffle tree.  The
+// order depends only on the group's size.  Groups with done[g] set (stored
+// whole by the column presum) are skipped.
+constexpr int kDetSerial = 8;
+
 template <typename T, int NPOL, bool UNIT>
 __global__ __launch_bounds__(256) void k_presum_det(int64_t n_groups, const int32_t *group_start,
                                                     const int32_t *order, const T *vis,
-                                                    const T *weight, cpx<T> *A) {
+                                                    const T *weight, cpx<T> *A,
+                                                    const uint8_t *done) {
+    const int lane = threadIdx.x & 63;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= n_groups) return;
-    cpx<T> a[NPOL];
-    for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
-    for (int32_t i = group_start[g]; i < group_start[g + 1]; ++i) {
+    const bool mine = g < n_groups && !(done && done[g]);
+    int32_t b = 0, e = 0;
+    if (mine) {
+        b = group_start[g];
+        e = group_start[g + 1];
+    }
+    auto add = [&](cpx<T> *a, int32_t i) {
         const int64_t pair = order[i];
         for (int p = 0; p < NPOL; ++p) {
             const T W = weight ? weight[pair * NPOL + p] : (T)1;
@@ -1065,14 +1083,36 @@ __global__ __launch_bounds__(256) void k_presum_det(int64_t n_groups, const int3
                 a[p].y += W * v[1];
             }
         }
+    };
+    const bool big = mine && e - b > kDetSerial;
+    if (mine && !big) {
+        cpx<T> a[NPOL];
+        for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
+        for (int32_t i = b; i < e; ++i) add(a, i);
+        for (int p = 0; p < NPOL; ++p) A[g * NPOL + p] = a[p];
     }
-    for (int p = 0; p < NPOL; ++p) A[g * NPOL + p] = a[p];
+    for (uint64_t todo = __ballot(big); todo; todo &= todo - 1) {
+        const int l = __builtin_ctzll(todo);
+        const int32_t bb = __shfl(b, l), ee = __shfl(e, l);
+        cpx<T> a[NPOL];
+        for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
+        for (int32_t i = bb + lane; i < ee; i += 64) add(a, i);
+        for (int off = 32; off > 0; off >>= 1)
+            for (int p = 0; p < NPOL; ++p) {
+                a[p].x += __shfl_down(a[p].x, off);
+                a[p].y += __shfl_down(a[p].y, off);
+            }
+        if (lane == 0) {
+            const int64_t gl = g - lane + l;
+            for (int p = 0; p < NPOL; ++p) A[gl * NPOL + p] = a[p];
+        }
+    }
 }
 
 // Sums of weights: block (c, k) adds the kept weights of channel c over
 // rows k * 256 + t + i * 256 * kDetRowBlocks, then a fixed tree over its
-// threads writes part[c][k][pol]; one thread per (plane, pol) adds the
-// partials of the plane's channels in channel and block order.
+// threads writes part[c][k][pol]; k_sumwt_finish adds the partials of each
+// plane's channels.
 template <typename T, int NPOL>
 __global__ __launch_bounds__(256) void k_sumwt_part(int64_t nrow, int32_t nchan,
                                                     const int32_t *pair_group, const T *weight,
@@ -1100,17 +1140,26 @@ __global__ __launch_bounds__(256) void k_sumwt_part(int64_t nrow, int32_t nchan,
         for (int p = 0; p < NPOL; ++p) part[((int64_t)c * kDetRowBlocks + k) * NPOL + p] = red[0][p];
 }
 
-__global__ void k_sumwt_finish(int32_t nchan, const ChanConst *cc, const double *part,
-                               int32_t nplane, int32_t npol, double *sumwt) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nplane * npol) return;
-    const int plane = t / npol, p = t % npol;
+// One workgroup per (plane, pol): its threads add strided partials of the
+// plane's channels, then a fixed tree over the threads.
+__global__ __launch_bounds__(256) void k_sumwt_finish(int32_t nchan, const ChanConst *cc,
+                                                      const double *part, int32_t npol,
+                                                      double *sumwt) {
+    __shared__ double red[256];
+    const int plane = blockIdx.x / npol, p = blockIdx.x % npol;
     double s = 0.0;
-    for (int c = 0; c < nchan; ++c) {
-        if (cc[c].plane != plane) continue;
-        for (int k = 0; k < kDetRowBlocks; ++k) s += part[((int64_t)c * kDetRowBlocks + k) * npol + p];
+    const int64_t n = (int64_t)nchan * kDetRowBlocks;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const int c = (int)(i / kDetRowBlocks);
+        if (cc[c].plane == plane) s += part[i * npol + p];
     }
-    sumwt[t] += s;
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sumwt[blockIdx.x] += red[0];
 }
 
 // ---------------------------------------------------------------------------
@@ -1128,17 +1177,17 @@ static hipError_t presum_t(const lr_plan *P, const VisArgs &v, void *A, double *
         col_shape(P->n_pairs, P->period, ncb, nb);
         dim3 g2((unsigned)nb);
         if (!sums)
-            hipLaunchKernelGGL((k_presum_col<T, NPOL, false, false>), g2, blk, 0, s,
+            hipLaunchKernelGGL((k_presum_col<T, NPOL, false, false, false>), g2, blk, 0, s,
                                P->n_pairs, P->period, ncb, P->pair_group, P->groups, vis, wt,
-                               (cpx<T> *)A, sumwt, cnt);
+                               (cpx<T> *)A, sumwt, cnt, nullptr);
         else if (v.unit_vis)
-            hipLaunchKernelGGL((k_presum_col<T, NPOL, true, true>), g2, blk, 0, s, P->n_pairs,
-                               P->period, ncb, P->pair_group, P->groups, vis, wt, (cpx<T> *)A,
-                               sumwt, cnt);
-        else
-            hipLaunchKernelGGL((k_presum_col<T, NPOL, false, true>), g2, blk, 0, s,
+            hipLaunchKernelGGL((k_presum_col<T, NPOL, true, true, false>), g2, blk, 0, s,
                                P->n_pairs, P->period, ncb, P->pair_group, P->groups, vis, wt,
-                               (cpx<T> *)A, sumwt, cnt);
+                               (cpx<T> *)A, sumwt, cnt, nullptr);
+        else
+            hipLaunchKernelGGL((k_presum_col<T, NPOL, false, true, false>), g2, blk, 0, s,
+                               P->n_pairs, P->period, ncb, P->pair_group, P->groups, vis, wt,
+                               (cpx<T> *)A, sumwt, cnt, nullptr);
         return hipGetLastError();
     }
     if (!sums)
@@ -1344,28 +1393,53 @@ hipError_t launch_expand(const lr_plan *P, const void *Vg, void *vis, const void
     return expand_t<float>(P, Vg, vis, weight, npol, s);
 }
 
+__global__ void k_clear_u8(uint8_t *p, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
 template <typename T, int NPOL>
-static hipError_t presum_det_t(const lr_plan *P, const VisArgs &v, void *A, hipStream_t s) {
+static hipError_t presum_det_t(const lr_plan *P, const VisArgs &v, void *A, uint8_t *done,
+                               int64_t *counters, hipStream_t s) {
     dim3 grd(nblk(P->n_groups, 256)), blk(256);
     const T *vis = (const T *)v.vis;
     const T *wt = (const T *)v.weight;
+    const bool col = P->period > 0 && !v.unit_vis;
+    if (col) {
+        // the column presum stores the groups it holds whole (and counts the
+        // samples: integer atomics are exact); the rest are gathered below
+        int64_t ncb, nb;
+        col_shape(P->n_pairs, P->period, ncb, nb);
+        hipLaunchKernelGGL(k_clear_u8, grd, blk, 0, s, done, P->n_groups);
+        hipLaunchKernelGGL((k_presum_col<T, NPOL, false, true, true>), dim3((unsigned)nb), blk,
+                           0, s, P->n_pairs, P->period, ncb, P->pair_group, P->groups, vis, wt,
+                           (cpx<T> *)A, (double *)nullptr, (long long *)counters, done);
+    } else if (counters) {
+        VisArgs w{nullptr, v.weight, v.npol, 0};
+        hipError_t e = presum_np<T>(P, w, nullptr, nullptr, counters, false, s);
+        if (e != hipSuccess) return e;
+    }
     if (v.unit_vis)
         hipLaunchKernelGGL((k_presum_det<T, NPOL, true>), grd, blk, 0, s, P->n_groups,
-                           P->group_start, P->order, vis, wt, (cpx<T> *)A);
+                           P->group_start, P->order, vis, wt, (cpx<T> *)A, (const uint8_t *)nullptr);
     else
         hipLaunchKernelGGL((k_presum_det<T, NPOL, false>), grd, blk, 0, s, P->n_groups,
-                           P->group_start, P->order, vis, wt, (cpx<T> *)A);
+                           P->group_start, P->order, vis, wt, (cpx<T> *)A,
+                           (const uint8_t *)(col ? done : nullptr));
     return hipGetLastError();
 }
 
 hipError_t launch_presum_det(const lr_plan *P, const VisArgs &v, int precision, void *A,
-                             hipStream_t s) {
-    if (P->n_groups == 0) return hipSuccess;
+                             uint8_t *done, int64_t *counters, hipStream_t s) {
+    if (P->n_pairs == 0) return hipSuccess;
     const bool f64 = precision == LR_F64;
     switch (v.npol) {
-        case 1: return f64 ? presum_det_t<double, 1>(P, v, A, s) : presum_det_t<float, 1>(P, v, A, s);
-        case 2: return f64 ? presum_det_t<double, 2>(P, v, A, s) : presum_det_t<float, 2>(P, v, A, s);
-        default: return f64 ? presum_det_t<double, 4>(P, v, A, s) : presum_det_t<float, 4>(P, v, A, s);
+        case 1: return f64 ? presum_det_t<double, 1>(P, v, A, done, counters, s)
+                           : presum_det_t<float, 1>(P, v, A, done, counters, s);
+        case 2: return f64 ? presum_det_t<double, 2>(P, v, A, done, counters, s)
+                           : presum_det_t<float, 2>(P, v, A, done, counters, s);
+        default: return f64 ? presum_det_t<double, 4>(P, v, A, done, counters, s)
+                            : presum_det_t<float, 4>(P, v, A, done, counters, s);
     }
 }
 
@@ -1385,9 +1459,8 @@ hipError_t launch_sumwt_det(const lr_plan *P, const void *weight, int precision,
         case 2: f64 ? sumwt_part_t<double, 2>(P, weight, part, s) : sumwt_part_t<float, 2>(P, weight, part, s); break;
         default: f64 ? sumwt_part_t<double, 4>(P, weight, part, s) : sumwt_part_t<float, 4>(P, weight, part, s);
     }
-    const int n = nplane * npol;
-    hipLaunchKernelGGL(k_sumwt_finish, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                       P->nchan, P->cc, part, nplane, npol, sumwt);
+    hipLaunchKernelGGL(k_sumwt_finish, dim3((unsigned)(nplane * npol)), dim3(256), 0, s,
+                       P->nchan, P->cc, part, npol, sumwt);
     return hipGetLastError();
 }
 

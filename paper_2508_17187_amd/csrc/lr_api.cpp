@@ -434,8 +434,9 @@ size_t lr_workspace_bytes(int op, const lr_cf_spec *spec, const lr_grid_spec *gr
     size_t per = 0;
     if (op == LR_OP_GRID || op == LR_OP_PSF || op == LR_OP_DEGRID)
         per = al256((size_t)std::max<int64_t>(n_groups, 1) * grid->npol * cplx_bytes(precision));
-    // partial sums of weights of the deterministic mode
+    // partial sums of weights and group flags of the deterministic mode
     if (op == LR_OP_GRID || op == LR_OP_SUMWT) per += det_bytes(vis->nchan, grid->npol);
+    if (op == LR_OP_GRID) per += al256((size_t)std::max<int64_t>(n_groups, 1));
     return plan + per + 256;
 }
 
@@ -693,7 +694,8 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
     size_t plan_need = vis->plan ? 0 : al256(plan_total(cf, vis));
     // deterministic order (lr_set_deterministic): not for the PSF
     const bool det = g_det.load() != 0 && !psf;
-    const size_t d_bytes = det ? det_bytes(vis->nchan, vis->npol) : 0;
+    const size_t d_bytes =
+        det ? det_bytes(vis->nchan, vis->npol) + al256((size_t)std::max<int64_t>(ng_bound, 1)) : 0;
     if (work_bytes < plan_need + a_bytes + d_bytes)
         return fail(LR_E_WORKSPACE, "workspace needs %zu bytes, got %zu",
                     plan_need + a_bytes + d_bytes, work_bytes);
@@ -711,17 +713,15 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
         // every sum in a fixed order: group sums stored per group, sums of
         // weights from fixed partials, one workgroup per tile
         double *part = (double *)((char *)A + a_bytes);
+        uint8_t *done = (uint8_t *)part + det_bytes(vis->nchan, vis->npol);
         hipError_t e = launch_grid_setup(P, nullptr, 0, set ? sumwt : nullptr,
                                          sizeof(double) * cf->grid.nplane * vis->npol,
                                          set ? counters : nullptr, grid, precision, vis->npol,
                                          cf->grid.nx, cf->grid.ny, set, s);
-        if (e == hipSuccess && counters)
-            e = launch_counts(P, vis->weight, precision, vis->npol, nullptr, counters,
-                              cf->grid.nplane, s);
         if (e == hipSuccess && sumwt)
             e = launch_sumwt_det(P, vis->weight, precision, vis->npol, cf->grid.nplane, part,
                                  sumwt, s);
-        if (e == hipSuccess) e = launch_presum_det(P, va, precision, A, s);
+        if (e == hipSuccess) e = launch_presum_det(P, va, precision, A, done, counters, s);
         if (e == hipSuccess) {
             prof.begin();
             e = launch_grid(P, view_of(cf), A, grid, precision, vis->npol, cf->grid.nx,

@@ -2,12 +2,14 @@
 
 With the mode on, repeated gridding calls on the same inputs give
 bit-identical grids and sums of weights, also with other work running on
-another stream and with a transient instead of an explicit plan; the
+another stream, with a transient instead of an explicit plan and with rows
+in time order (column presum) or shuffled (sorted-order gather); the
 results match the oracle within the form's tolerance and the default mode
 up to rounding order; lr_sumwt gives the same sums bit for bit; and a
 serving job's result is bit-identical alone and in the mix.
 """
 
+import copy
 import time
 
 import numpy as np
@@ -59,7 +61,13 @@ def workloads():
                             fg_hz=[2.4e9, 3.6e9], cfg_id=211, pointing_sigma=3e-5)
     rng = np.random.default_rng(211)
     b.weight[rng.random(b.weight.shape) < 0.05] = 0.0
-    return {"shared": a, "awp": b}
+    # rows in random order have no period: every group sum takes the
+    # sorted-order gather instead of the column presum
+    c = copy.deepcopy(a)
+    perm = rng.permutation(a.obs.nrow)
+    c.obs.uvw, c.obs.ant1, c.obs.ant2 = a.obs.uvw[perm], a.obs.ant1[perm], a.obs.ant2[perm]
+    c.vis, c.weight = a.vis[perm], a.weight[perm]
+    return {"shared": a, "awp": b, "shuffled": c}
 
 
 WL = {}
@@ -82,7 +90,7 @@ def run(cf, v, p, wl, overwrite=True):
     return g.cpu().numpy(), sw.cpu().numpy(), cnt.cpu().numpy()
 
 
-@pytest.mark.parametrize("name", ["shared", "awp"])
+@pytest.mark.parametrize("name", ["shared", "awp", "shuffled"])
 @pytest.mark.parametrize("form", ["f64", "f32"])
 def test_repeated_calls_are_bit_identical(det, name, form):
     wl = get(name)
