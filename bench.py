@@ -80,6 +80,7 @@ def run_form(wl, form, steps, warmup, ev):
     wg = lr._work(lr.LR_OP_GRID, cf, v, p, None)
     wd = lr._work(lr.LR_OP_DEGRID, cf, vout, p, None)
     info = plan.info()
+    sample_taps = per_sample_taps(cf, v)
 
     def step(prof=None, marks=None):
         if marks:
@@ -153,8 +154,29 @@ def run_form(wl, form, steps, warmup, ev):
         "n_groups": info["n_groups"],
         "n_kept_pairs": info["n_kept"],
         "taps": info["taps"],
+        "sample_taps": sample_taps,
     }
     return res, g, vout.vis
+
+
+def per_sample_taps(cf, v):
+    """Kernel taps of the method as written, without merging: S_k^2 for
+    every kept sample (row, channel, pol with nonzero weight), S_k the
+    support of the sample's plane (from the index map and the table
+    layout: a plane of support S holds (O + 1)^2 S^2 entries)."""
+    import numpy as np
+    import torch
+    from paper_2508_17187_amd import lr
+    m = lr.lr_debug_map(cf, v)
+    _, _, ne, po = cf.layout()
+    ends = np.append(po[1:], ne)
+    s2 = torch.as_tensor((ends - po) // (cf.spec.oversample + 1) ** 2, device=m.device)
+    plane = m[..., 7].long() * cf.spec.n_w + m[..., 4].long()
+    keep = m[..., 6] != 0
+    npol = v.npol
+    live = (v.weight != 0).sum(-1) if v.weight is not None else torch.full_like(plane, npol)
+    taps = torch.where(keep, s2[plane.clamp(0, len(po) - 1)] * live, 0)
+    return int(taps.sum().item())
 
 
 ELEM = {"f64": 16, "f32": 8, "f16cf": 4, "bf16cf": 4}
@@ -194,17 +216,25 @@ def gridder_roofline(wl, form, r, with_traffic=True):
             traffic = tr["hbm_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         pass
+    # the vector-ALU roof in complex multiply-adds (8 flops each) per second,
+    # for the taps the method takes per sample and for those the merged
+    # groups execute
+    valu = {"peak_cmac_per_s": PEAK[form] / 8.0,
+            "per_sample_cmac_per_s": r["sample_taps"] / t,
+            "per_sample_frac": r["sample_taps"] / t / (PEAK[form] / 8.0),
+            "executed_cmac_per_s": npol * r["taps"] / t,
+            "executed_frac": npol * r["taps"] / t / (PEAK[form] / 8.0)}
     if hbm:
         return {"bound": "hbm", "kernel": "k_grid_tile (gridder)", "achieved": bytes_ / t / 1e9,
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": bytes_ / t / HBM_PEAK,
                 "traffic": traffic, "algorithmic_bytes_per_launch": bytes_,
                 "algorithmic_flops_per_launch": flops,
-                "alu_frac": flops / t / PEAK[form], "kernel_ms": r["grid_kernel_ms"]}
+                "alu_frac": flops / t / PEAK[form], "valu": valu, "kernel_ms": r["grid_kernel_ms"]}
     return {"bound": "alu", "kernel": "k_grid_tile (gridder)", "achieved": flops / t / 1e12,
             "peak": PEAK[form] / 1e12, "unit": "TFLOP/s", "frac": flops / t / PEAK[form],
             "traffic": traffic, "algorithmic_bytes_per_launch": bytes_,
             "algorithmic_flops_per_launch": flops, "hbm_frac": bytes_ / t / HBM_PEAK,
-            "kernel_ms": r["grid_kernel_ms"]}
+            "valu": valu, "kernel_ms": r["grid_kernel_ms"]}
 
 
 def gridding_roofline(wl, form, r):
