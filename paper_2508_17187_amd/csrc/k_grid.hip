@@ -1096,7 +1096,41 @@ __global__ __launch_bounds__(256) void k_presum_det(int64_t n_groups, const int3
         const int32_t bb = __shfl(b, l), ee = __shfl(e, l);
         cpx<T> a[NPOL];
         for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
-        for (int32_t i = bb + lane; i < ee; i += 64) add(a, i);
+        // members i, i + 64, i + 128, i + 192 are loaded before any is added
+        // (the adds keep that order)
+        constexpr int U = 4;
+        for (int32_t i0 = bb + lane; i0 < ee; i0 += 64 * U) {
+            int64_t pr[U];
+            T w[U][NPOL];
+            cpx<T> x[U][NPOL];
+            for (int u = 0; u < U; ++u) {
+                const int32_t i = i0 + 64 * u;
+                pr[u] = i < ee ? (int64_t)order[i] : -1;
+            }
+            for (int u = 0; u < U; ++u) {
+                if (pr[u] < 0) continue;
+                for (int p = 0; p < NPOL; ++p) {
+                    w[u][p] = weight ? weight[pr[u] * NPOL + p] : (T)1;
+                    if (!UNIT) {
+                        const T *v = vis + 2 * (pr[u] * NPOL + p);
+                        x[u][p] = {v[0], v[1]};
+                    }
+                }
+            }
+            for (int u = 0; u < U; ++u) {
+                if (pr[u] < 0) continue;
+                for (int p = 0; p < NPOL; ++p) {
+                    const T W = w[u][p];
+                    if (W == (T)0) continue;
+                    if (UNIT) {
+                        a[p].x += W;
+                    } else {
+                        a[p].x += W * x[u][p].x;
+                        a[p].y += W * x[u][p].y;
+                    }
+                }
+            }
+        }
         for (int off = 32; off > 0; off >>= 1)
             for (int p = 0; p < NPOL; ++p) {
                 a[p].x += __shfl_down(a[p].x, off);
