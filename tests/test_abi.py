@@ -160,3 +160,24 @@ def test_calibration_calls_validate_on_the_host(L):
     assert solve(max_iter=-1) == L.LR_E_ARG
     assert solve(n=-1) == L.LR_E_ARG
     assert b"n_problems" in lib.lr_last_error()
+
+
+def test_deterministic_setting_and_its_workspace(L):
+    """lr_set_deterministic is host-only and process-wide; the gridding
+    workspace always has room for the deterministic mode's partial sums of
+    weights (nchan x 64 row blocks x npol doubles) and its one-byte group
+    flags, so a workspace sized once serves both modes."""
+    lib = L.lib()
+    prev = lib.lr_deterministic()
+    try:
+        assert lib.lr_set_deterministic(1) == 0 and lib.lr_deterministic() == 1
+        assert lib.lr_set_deterministic(0) == 0 and lib.lr_deterministic() == 0
+    finally:
+        lib.lr_set_deterministic(prev)
+    g, s, fg = _specs(L)
+    nrow, nchan, npol = 1000, 16, 4
+    v = L.VisDesc(nrow=nrow, nchan=nchan, npol=npol)
+    ws = {op: lib.lr_workspace_bytes(op, C.byref(s), C.byref(g), C.byref(v), L.LR_F32)
+          for op in (L.LR_OP_GRID, L.LR_OP_DEGRID)}
+    al = lambda n: (n + 255) // 256 * 256
+    assert ws[L.LR_OP_GRID] - ws[L.LR_OP_DEGRID] == al(nchan * 64 * npol * 8) + al(nrow * nchan)
