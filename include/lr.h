@@ -203,12 +203,19 @@ lr_status lr_plan_info(const lr_plan *plan, int64_t *n_groups, int64_t *n_kept,
  * lr_grid, lr_grid_overwrite and lr_sumwt call forms its sums in an order
  * that does not depend on scheduling, so that repeated calls on the same
  * inputs (alone or beside other work on the device) give bit-identical
- * grids and sums of weights: group sums one group at a time in the plan's
- * sorted order, sums of weights from fixed per-(channel, row block)
- * partials added in channel order, and one workgroup per grid tile instead
- * of atomic flushes of tiles shared by several chunks.  Slower; the results
- * equal the default mode's up to FP rounding order.  lr_make_psf keeps its
- * atomic mirror adds.  lr_deterministic returns the current setting. */
+ * grids and sums of weights.  Group sums (the weighted sum of each group of
+ * identical samples of the binning step) are stored, never added with
+ * atomics: along tracks for groups one wavefront holds whole, otherwise in
+ * the plan's sorted order with a summation order fixed by the group's size;
+ * sums of weights come from fixed per-(channel, row block) partials and
+ * fixed trees; each grid tile is written by one workgroup, which takes the
+ * tile's chunks in order, instead of atomic flushes of tiles shared by
+ * several chunks.  Slower (about 2.7x per gridding call on data whose
+ * samples merge into large groups); the results equal the default mode's
+ * up to FP rounding order.  The workspace size of LR_OP_GRID and
+ * LR_OP_SUMWT always includes what this mode needs.  lr_make_psf keeps its
+ * atomic mirror adds.  Returns LR_OK.  lr_deterministic returns the current
+ * setting (0 or 1). */
 lr_status lr_set_deterministic(int32_t on);
 int32_t lr_deterministic(void);
 
