@@ -588,7 +588,7 @@ static void col_shape(int64_t n_pairs, int64_t L, int64_t &ncb, int64_t &blocks)
 // by the call's set-up kernel before it).
 struct TileArgs {
     const GroupMeta *groups;
-    const int32_t *tp_group, *chunk_start, *chunk_tile, *chunk_excl, *tile_state;
+    const int32_t *tp_group, *chunk_start, *chunk_tile, *chunk_excl, *chunk_order, *tile_state;
     const void *A;
     void *grid;
     CFView cf;
@@ -649,7 +649,9 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     __shared__ TileItem items[kChunkMax];
     __shared__ cpx<T> avs[kChunkMax * NPOL];
     __shared__ GroupMeta gms[PO ? kChunkMax : 1];
-    const int c0 = blockIdx.x;
+    // workgroups take the chunks largest first; those after the chunks
+    // (GRID_SET) clear the tiles without pairs
+    const int c0 = (int)blockIdx.x < a.n_chunks ? a.chunk_order[blockIdx.x] : (int)blockIdx.x;
     if (!PSF && c0 >= a.n_chunks) {      // GRID_SET: tiles without pairs
         const int tile = c0 - a.n_chunks;
         if (a.tile_state[tile] == 0)
@@ -1304,7 +1306,7 @@ hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *
     const int64_t nc = P->n_chunks + (set ? P->n_tiles : 0);
     if (nc == 0) return hipSuccess;
     TileArgs ta{P->groups, P->tp_group, P->chunk_start, P->chunk_tile, P->chunk_excl,
-                P->tile_state, A, grid, cf, nx, ny, (nx + kTile - 1) / kTile,
+                P->chunk_order, P->tile_state, A, grid, cf, nx, ny, (nx + kTile - 1) / kTile,
                 (ny + kTile - 1) / kTile, (int64_t)nx * ny, (int32_t)P->n_chunks,
                 set ? 1 : 0};
     bool po = P->po != 0;

@@ -310,6 +310,19 @@ __global__ void k_chunk_excl(const uint32_t *keys, int32_t *chunk_start, int64_t
     chunk_excl[c] = (first && last) ? 1 : 0;
 }
 
+// Work estimate of each chunk: the footprint cells of its pairs inside the
+// tile, complemented so that an ascending sort puts the largest first; the
+// chunk ids ride along.
+__global__ void k_chunk_cost(const int32_t *chunk_start, const int32_t *pair_cost,
+                             int64_t n_chunks, uint32_t *key, int32_t *id) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    uint32_t w = 0;
+    for (int32_t i = chunk_start[c]; i < chunk_start[c + 1]; ++i) w += (uint32_t)pair_cost[i];
+    key[c] = ~w;
+    id[c] = (int32_t)c;
+}
+
 __global__ void k_chunk_end(int32_t *chunk_start, int64_t n_chunks, int64_t n) {
     if (threadIdx.x == 0) chunk_start[n_chunks] = (int32_t)n;
 }
@@ -438,6 +451,7 @@ PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max, int64_t n_
     L.chunk_start = take(sizeof(int32_t) * (ntp + 1));
     L.chunk_tile = take(sizeof(int32_t) * ntp);
     L.chunk_excl = take(sizeof(int32_t) * ntp);
+    L.chunk_order = take(sizeof(int32_t) * ntp);
     L.tile_state = take(sizeof(int32_t) * std::max<int64_t>(n_tiles, 1));
     L.shared_tiles = take(sizeof(int32_t) * std::max<int64_t>(n_tiles, 1));
     L.persistent = off;
@@ -481,6 +495,7 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->chunk_start = (int32_t *)(buf + L.chunk_start);
     P->chunk_tile = (int32_t *)(buf + L.chunk_tile);
     P->chunk_excl = (int32_t *)(buf + L.chunk_excl);
+    P->chunk_order = (int32_t *)(buf + L.chunk_order);
     P->tile_state = (int32_t *)(buf + L.tile_state);
     P->n_tiles = tile_count(g.nx, g.ny, g.nplane);
     P->shared_tiles = (int32_t *)(buf + L.shared_tiles);
@@ -566,6 +581,13 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     hipLaunchKernelGGL(k_chunk_excl, dim3(blocks(nch, 256)), dim3(256), 0, s, tk_b,
                        P->chunk_start, nch, ntp, P->chunk_excl);
     hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(64), 0, s, P->chunk_start, nch, ntp);
+    // the gridder launches chunks largest first (a stable sort: ties keep
+    // tile order), so the long ones do not trail the launch
+    hipLaunchKernelGGL(k_chunk_cost, dim3(blocks(nch, 256)), dim3(256), 0, s, P->chunk_start,
+                       vals_a, nch, tk_a, flags);
+    e = rocprim::radix_sort_pairs(temp, temp_bytes, tk_a, (uint32_t *)scan, flags,
+                                  P->chunk_order, (size_t)nch, 0, 32, s);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_tile_state, dim3(blocks(nch, 256)), dim3(256), 0, s, P->chunk_tile,
                        P->chunk_excl, nch, P->tile_state);
     if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
