@@ -649,9 +649,11 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     __shared__ TileItem items[kChunkMax];
     __shared__ cpx<T> avs[kChunkMax * NPOL];
     __shared__ GroupMeta gms[PO ? kChunkMax : 1];
-    // workgroups take the chunks largest first; those after the chunks
-    // (GRID_SET) clear the tiles without pairs
-    const int c0 = (int)blockIdx.x < a.n_chunks ? a.chunk_order[blockIdx.x] : (int)blockIdx.x;
+    // workgroups take the chunks in the plan's order (largest first, or tile
+    // order without chunk_order); those after the chunks (GRID_SET) clear
+    // the tiles without pairs
+    const int c0 = a.chunk_order && (int)blockIdx.x < a.n_chunks ? a.chunk_order[blockIdx.x]
+                                                                  : (int)blockIdx.x;
     if (!PSF && c0 >= a.n_chunks) {      // GRID_SET: tiles without pairs
         const int tile = c0 - a.n_chunks;
         if (a.tile_state[tile] == 0)

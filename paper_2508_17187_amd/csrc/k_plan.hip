@@ -310,17 +310,23 @@ __global__ void k_chunk_excl(const uint32_t *keys, int32_t *chunk_start, int64_t
     chunk_excl[c] = (first && last) ? 1 : 0;
 }
 
-// Work estimate of each chunk: the footprint cells of its pairs inside the
-// tile, complemented so that an ascending sort puts the largest first; the
-// chunk ids ride along.
-__global__ void k_chunk_cost(const int32_t *chunk_start, const int32_t *pair_cost,
-                             int64_t n_chunks, uint32_t *key, int32_t *id) {
-    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+// Work estimate of each chunk (one wavefront per chunk): the footprint
+// cells of its pairs inside the tile, complemented so that an ascending
+// sort puts the largest first; the chunk ids ride along.
+__global__ __launch_bounds__(256) void k_chunk_cost(const int32_t *chunk_start,
+                                                    const int32_t *pair_cost, int64_t n_chunks,
+                                                    uint32_t *key, int32_t *id) {
+    const int64_t c = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int lane = threadIdx.x & 63;
     if (c >= n_chunks) return;
+    const int32_t s0 = chunk_start[c], n = chunk_start[c + 1] - s0;
     uint32_t w = 0;
-    for (int32_t i = chunk_start[c]; i < chunk_start[c + 1]; ++i) w += (uint32_t)pair_cost[i];
-    key[c] = ~w;
-    id[c] = (int32_t)c;
+    for (int i = lane; i < n; i += 64) w += (uint32_t)pair_cost[s0 + i];
+    for (int off = 32; off > 0; off >>= 1) w += __shfl_xor(w, off);
+    if (lane == 0) {
+        key[c] = ~w;
+        id[c] = (int32_t)c;
+    }
 }
 
 __global__ void k_chunk_end(int32_t *chunk_start, int64_t n_chunks, int64_t n) {
@@ -474,7 +480,7 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
                              const ChanConst *d_cc, const MapGeom &g, const KeyLayout &kl,
                              const CFView &cf, const int32_t *ant1, const int32_t *ant2,
                              int32_t nant, const double *ant_dlm, double du_dl,
-                             double dv_dm, int32_t per, int32_t cmax, hipStream_t s) {
+                             double dv_dm, int32_t per, int32_t cmax, bool lpt, hipStream_t s) {
     hipError_t e;
     int64_t n = P->n_pairs;
     uint64_t *keys_a = (uint64_t *)(buf + L.keys_a), *keys_b = (uint64_t *)(buf + L.keys_b);
@@ -581,13 +587,19 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     hipLaunchKernelGGL(k_chunk_excl, dim3(blocks(nch, 256)), dim3(256), 0, s, tk_b,
                        P->chunk_start, nch, ntp, P->chunk_excl);
     hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(64), 0, s, P->chunk_start, nch, ntp);
-    // the gridder launches chunks largest first (a stable sort: ties keep
-    // tile order), so the long ones do not trail the launch
-    hipLaunchKernelGGL(k_chunk_cost, dim3(blocks(nch, 256)), dim3(256), 0, s, P->chunk_start,
-                       vals_a, nch, tk_a, flags);
-    e = rocprim::radix_sort_pairs(temp, temp_bytes, tk_a, (uint32_t *)scan, flags,
-                                  P->chunk_order, (size_t)nch, 0, 32, s);
-    if (e != hipSuccess) return e;
+    // with a kernel table the last-level cache holds, the gridder launches
+    // chunks largest first (a stable sort: ties keep tile order), so the
+    // long ones do not trail the launch; a larger table keeps tile order,
+    // whose neighbouring chunks share kernel planes in the cache
+    if (lpt && nch > 0) {
+        hipLaunchKernelGGL(k_chunk_cost, dim3(blocks(nch * 64, 256)), dim3(256), 0, s,
+                           P->chunk_start, vals_a, nch, tk_a, flags);
+        e = rocprim::radix_sort_pairs(temp, temp_bytes, tk_a, (uint32_t *)scan, flags,
+                                      P->chunk_order, (size_t)nch, 0, 32, s);
+        if (e != hipSuccess) return e;
+    } else {
+        P->chunk_order = nullptr;
+    }
     hipLaunchKernelGGL(k_tile_state, dim3(blocks(nch, 256)), dim3(256), 0, s, P->chunk_tile,
                        P->chunk_excl, nch, P->tile_state);
     if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;

@@ -358,8 +358,11 @@ lr_status build_plan(const lr_cf *cf, const lr_vis *v, int psf, void *buf, size_
     MapGeom g = map_geom(cf, v->nchan, psf);
     double du_dl = 1.0 / ((double)cf->grid.nx * cf->grid.cell_l);
     double dv_dm = 1.0 / ((double)cf->grid.ny * cf->grid.cell_m);
+    // largest-first chunk order for kernel tables up to the size of the
+    // last-level cache (256 MB)
+    const bool lpt = (size_t)cf->n_elems * cf->elem_bytes <= ((size_t)256 << 20);
     e = build_plan_device(P, b, L, v->uvw, d_cc, g, kl, view_of(cf), v->ant1, v->ant2,
-                          v->nant, v->ant_dlm, du_dl, dv_dm, chunk_pairs(), kChunkCells, s);
+                          v->nant, v->ant_dlm, du_dl, dv_dm, chunk_pairs(), kChunkCells, lpt, s);
     if (e == hipErrorInvalidValue)
         return fail(LR_E_RANGE, "plan tile table overflow");
     if (e != hipSuccess) return dev_fail(e, "plan build");

@@ -142,7 +142,8 @@ struct lr_plan {
     int32_t *chunk_start;      // [n_chunks + 1] first pair of each gridder chunk
     int32_t *chunk_tile;       // [n_chunks] tile id: (plane * nty + ty) * ntx + tx
     int32_t *chunk_excl;       // [n_chunks] 1 when the chunk holds all pairs of its tile
-    int32_t *chunk_order;      // [n_chunks] chunks by estimated work, largest first
+    int32_t *chunk_order;      // [n_chunks] chunks by estimated work, largest first (null:
+                               // tile order, for kernel tables beyond the last-level cache)
     int32_t *tile_state;       // [n_tiles] 0 no pairs, 1 one exclusive chunk, 2 several chunks
     int64_t n_tiles;           // nplane * nty * ntx
     int32_t *shared_tiles;     // [n_shared] ids of the tiles in state 2

@@ -35,7 +35,7 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
                              const ChanConst *d_cc, const MapGeom &g, const KeyLayout &kl,
                              const CFView &cf, const int32_t *ant1, const int32_t *ant2,
                              int32_t nant, const double *ant_dlm, double du_dl,
-                             double dv_dm, int32_t per, int32_t cmax, hipStream_t s);
+                             double dv_dm, int32_t per, int32_t cmax, bool lpt, hipStream_t s);
 
 // ---- CF build (k_cf.hip) -----------------------------------------------------
 struct CFBuildArgs {
