@@ -205,12 +205,12 @@ lr_status lr_plan_info(const lr_plan *plan, int64_t *n_groups, int64_t *n_kept,
  * inputs (alone or beside other work on the device) give bit-identical
  * grids and sums of weights.  Group sums (the weighted sum of each group of
  * identical samples of the binning step) are stored, never added with
- * atomics: along tracks for groups one wavefront holds whole, otherwise in
- * the plan's sorted order with a summation order fixed by the group's size;
+ * atomics: along tracks for groups one wavefront holds whole, otherwise
+ * over fixed segments of the plan's sorted order, pieces joined in order;
  * sums of weights come from fixed per-(channel, row block) partials and
  * fixed trees; each grid tile is written by one workgroup, which takes the
  * tile's chunks in order, instead of atomic flushes of tiles shared by
- * several chunks.  Slower (about 2.7x per gridding call on data whose
+ * several chunks.  Slower (about 2.2x per gridding call on data whose
  * samples merge into large groups); the results equal the default mode's
  * up to FP rounding order.  The workspace size of LR_OP_GRID and
  * LR_OP_SUMWT always includes what this mode needs.  lr_make_psf keeps its

@@ -394,8 +394,8 @@ __global__ __launch_bounds__(256) void k_presum(
 // a whole group: a single-run group (kSingleRun) whose run neither began
 // before this wavefront's first step nor continues past its last one.
 // DET (deterministic order) stores those groups and sets done[g], and adds
-// nothing with atomics: the other groups are summed again afterwards, one
-// group at a time, by k_presum_det.
+// nothing with atomics: the other groups are summed again afterwards, in a
+// fixed order, by k_presum_seg and k_presum_join.
 constexpr int kColW = 8, kColT = 8, kColBlocks = 16;
 
 template <typename T, int NPOL, bool UNIT, bool SUMS, bool DET>
@@ -1053,98 +1053,108 @@ __global__ __launch_bounds__(256) void k_expand(int64_t n_pairs, const int32_t *
 
 // ---------------------------------------------------------------------------
 // Deterministic mode: sums whose order does not depend on scheduling.
-// Group sums, stored: lane i of a wavefront owns group 64 w + i.  A group
-// of at most kDetSerial members is added by its lane, one member at a time
-// in the plan's sorted order; a larger one by the whole wavefront, lane l
-// taking members l, l + 64, ... in order, then a fixed shuffle tree.  The
-// order depends only on the group's size.  Groups with done[g] set (stored
-// whole by the column presum) are skipped.
-constexpr int kDetSerial = 8;
+// Group sums over the members in the plan's sorted order (each group's
+// members are consecutive there), cut into fixed segments of kDetSeg
+// members, one wavefront per segment.  The wavefront takes its segment 64
+// members at a time, adds each run of equal group ids with a fixed
+// segmented scan over the lanes and carries the last run to the next 64.
+// A group the segment holds whole is stored; a group that crosses a segment
+// edge leaves its piece in part[segment][slot] (slot 0: the group began in
+// an earlier segment; 1: it begins here and continues), and k_presum_join
+// adds the pieces in segment order.  Groups with done[g] set (stored whole
+// by the column presum) are skipped.
 
-template <typename T, int NPOL, bool UNIT>
-__global__ __launch_bounds__(256) void k_presum_det(int64_t n_groups, const int32_t *group_start,
+template <typename T, int NPOL>
+__global__ __launch_bounds__(256) void k_presum_seg(int64_t n_kept, const int32_t *gidx,
+                                                    const int32_t *group_start,
                                                     const int32_t *order, const T *vis,
-                                                    const T *weight, cpx<T> *A,
-                                                    const uint8_t *done) {
+                                                    const T *weight, const uint8_t *done,
+                                                    cpx<T> *A, cpx<T> *part) {
     const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool mine = g < n_groups && !(done && done[g]);
-    int32_t b = 0, e = 0;
-    if (mine) {
-        b = group_start[g];
-        e = group_start[g + 1];
-    }
-    auto add = [&](cpx<T> *a, int32_t i) {
-        const int64_t pair = order[i];
-        for (int p = 0; p < NPOL; ++p) {
-            const T W = weight ? weight[pair * NPOL + p] : (T)1;
-            if (W == (T)0) continue;
-            if (UNIT) {
-                a[p].x += W;
-            } else {
-                const T *v = vis + 2 * (pair * NPOL + p);
-                a[p].x += W * v[0];
-                a[p].y += W * v[1];
-            }
-        }
+    const int64_t k = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t b0 = k * kDetSeg;
+    if (b0 >= n_kept) return;
+    const int64_t b1 = b0 + kDetSeg < n_kept ? b0 + kDetSeg : n_kept;
+    auto emit = [&](int g, const cpx<T> *v) {
+        const int64_t gs = group_start[g], ge = group_start[g + 1];
+        cpx<T> *dst = (gs >= b0 && ge <= b1) ? A + (int64_t)g * NPOL
+                                              : part + (k * 2 + (gs < b0 ? 0 : 1)) * NPOL;
+        for (int p = 0; p < NPOL; ++p) dst[p] = v[p];
     };
-    const bool big = mine && e - b > kDetSerial;
-    if (mine && !big) {
+    int carry_g = -1;
+    cpx<T> carry[NPOL];
+    for (int p = 0; p < NPOL; ++p) carry[p] = {(T)0, (T)0};
+    for (int64_t r0 = b0; r0 < b1; r0 += 64) {
+        const int64_t i = r0 + lane;
+        const bool valid = i < b1;
+        const int g = valid ? gidx[i] : -1;
+        const bool live = valid && !(done && done[g]);
+        const int key = live ? g : -1 - lane;       // skipped lanes never merge
         cpx<T> a[NPOL];
         for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
-        for (int32_t i = b; i < e; ++i) add(a, i);
-        for (int p = 0; p < NPOL; ++p) A[g * NPOL + p] = a[p];
-    }
-    for (uint64_t todo = __ballot(big); todo; todo &= todo - 1) {
-        const int l = __builtin_ctzll(todo);
-        const int32_t bb = __shfl(b, l), ee = __shfl(e, l);
-        cpx<T> a[NPOL];
-        for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
-        // members i, i + 64, i + 128, i + 192 are loaded before any is added
-        // (the adds keep that order)
-        constexpr int U = 4;
-        for (int32_t i0 = bb + lane; i0 < ee; i0 += 64 * U) {
-            int64_t pr[U];
-            T w[U][NPOL];
-            cpx<T> x[U][NPOL];
-            for (int u = 0; u < U; ++u) {
-                const int32_t i = i0 + 64 * u;
-                pr[u] = i < ee ? (int64_t)order[i] : -1;
-            }
-            for (int u = 0; u < U; ++u) {
-                if (pr[u] < 0) continue;
-                for (int p = 0; p < NPOL; ++p) {
-                    w[u][p] = weight ? weight[pr[u] * NPOL + p] : (T)1;
-                    if (!UNIT) {
-                        const T *v = vis + 2 * (pr[u] * NPOL + p);
-                        x[u][p] = {v[0], v[1]};
-                    }
-                }
-            }
-            for (int u = 0; u < U; ++u) {
-                if (pr[u] < 0) continue;
-                for (int p = 0; p < NPOL; ++p) {
-                    const T W = w[u][p];
-                    if (W == (T)0) continue;
-                    if (UNIT) {
-                        a[p].x += W;
-                    } else {
-                        a[p].x += W * x[u][p].x;
-                        a[p].y += W * x[u][p].y;
-                    }
-                }
-            }
-        }
-        for (int off = 32; off > 0; off >>= 1)
+        if (live) {
+            const int64_t pair = order[i];
             for (int p = 0; p < NPOL; ++p) {
-                a[p].x += __shfl_down(a[p].x, off);
-                a[p].y += __shfl_down(a[p].y, off);
+                const T W = weight ? weight[pair * NPOL + p] : (T)1;
+                if (W == (T)0) continue;
+                const T *v = vis + 2 * (pair * NPOL + p);
+                a[p].x = W * v[0];
+                a[p].y = W * v[1];
             }
-        if (lane == 0) {
-            const int64_t gl = g - lane + l;
-            for (int p = 0; p < NPOL; ++p) A[gl * NPOL + p] = a[p];
+        }
+        // the run carried from the previous 64 members continues here, or
+        // ended there
+        if (lane == 0 && carry_g >= 0) {
+            if (carry_g == key) {
+                for (int p = 0; p < NPOL; ++p) {
+                    a[p].x = carry[p].x + a[p].x;
+                    a[p].y = carry[p].y + a[p].y;
+                }
+            } else {
+                emit(carry_g, carry);
+            }
+        }
+        for (int off = 1; off < 64; off <<= 1) {
+            const int ko = __shfl_up(key, off);
+            const bool take = lane >= off && ko == key;
+            for (int p = 0; p < NPOL; ++p) {
+                const T x = __shfl_up(a[p].x, off), y = __shfl_up(a[p].y, off);
+                if (take) {
+                    a[p].x = x + a[p].x;
+                    a[p].y = y + a[p].y;
+                }
+            }
+        }
+        const int kn = __shfl_down(key, 1);
+        if (live && lane < 63 && kn != key) emit(g, a);
+        carry_g = __shfl(key, 63);
+        for (int p = 0; p < NPOL; ++p) {
+            carry[p].x = __shfl(a[p].x, 63);
+            carry[p].y = __shfl(a[p].y, 63);
         }
     }
+    if (lane == 0 && carry_g >= 0) emit(carry_g, carry);
+}
+
+// Groups that cross a segment edge: the piece of the first segment (slot
+// 1), then the later segments' pieces (slot 0), in segment order.
+template <typename T, int NPOL>
+__global__ __launch_bounds__(256) void k_presum_join(int64_t n_groups, const int32_t *group_start,
+                                                     const uint8_t *done, const cpx<T> *part,
+                                                     cpx<T> *A) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups || (done && done[g])) return;
+    const int64_t k0 = group_start[g] / kDetSeg, k1 = (group_start[g + 1] - 1) / kDetSeg;
+    if (k0 == k1) return;
+    cpx<T> a[NPOL];
+    for (int p = 0; p < NPOL; ++p) a[p] = part[(k0 * 2 + 1) * NPOL + p];
+    for (int64_t k = k0 + 1; k <= k1; ++k)
+        for (int p = 0; p < NPOL; ++p) {
+            const cpx<T> q = part[k * 2 * NPOL + p];
+            a[p].x += q.x;
+            a[p].y += q.y;
+        }
+    for (int p = 0; p < NPOL; ++p) A[g * NPOL + p] = a[p];
 }
 
 // Sums of weights: block (c, k) adds the kept weights of channel c over
@@ -1438,17 +1448,18 @@ __global__ void k_clear_u8(uint8_t *p, int64_t n) {
 
 template <typename T, int NPOL>
 static hipError_t presum_det_t(const lr_plan *P, const VisArgs &v, void *A, uint8_t *done,
-                               int64_t *counters, hipStream_t s) {
-    dim3 grd(nblk(P->n_groups, 256)), blk(256);
+                               void *part, int64_t *counters, hipStream_t s) {
+    dim3 blk(256);
     const T *vis = (const T *)v.vis;
     const T *wt = (const T *)v.weight;
-    const bool col = P->period > 0 && !v.unit_vis;
+    const bool col = P->period > 0;
     if (col) {
         // the column presum stores the groups it holds whole (and counts the
-        // samples: integer atomics are exact); the rest are gathered below
+        // samples: integer atomics are exact); the rest are summed below
         int64_t ncb, nb;
         col_shape(P->n_pairs, P->period, ncb, nb);
-        hipLaunchKernelGGL(k_clear_u8, grd, blk, 0, s, done, P->n_groups);
+        hipLaunchKernelGGL(k_clear_u8, dim3(nblk(P->n_groups, 256)), blk, 0, s, done,
+                           P->n_groups);
         hipLaunchKernelGGL((k_presum_col<T, NPOL, false, true, true>), dim3((unsigned)nb), blk,
                            0, s, P->n_pairs, P->period, ncb, P->pair_group, P->groups, vis, wt,
                            (cpx<T> *)A, (double *)nullptr, (long long *)counters, done);
@@ -1457,27 +1468,28 @@ static hipError_t presum_det_t(const lr_plan *P, const VisArgs &v, void *A, uint
         hipError_t e = presum_np<T>(P, w, nullptr, nullptr, counters, false, s);
         if (e != hipSuccess) return e;
     }
-    if (v.unit_vis)
-        hipLaunchKernelGGL((k_presum_det<T, NPOL, true>), grd, blk, 0, s, P->n_groups,
-                           P->group_start, P->order, vis, wt, (cpx<T> *)A, (const uint8_t *)nullptr);
-    else
-        hipLaunchKernelGGL((k_presum_det<T, NPOL, false>), grd, blk, 0, s, P->n_groups,
-                           P->group_start, P->order, vis, wt, (cpx<T> *)A,
-                           (const uint8_t *)(col ? done : nullptr));
+    if (P->n_kept == 0) return hipGetLastError();
+    const uint8_t *dn = col ? done : nullptr;
+    const int64_t n_seg = (P->n_kept + kDetSeg - 1) / kDetSeg;
+    hipLaunchKernelGGL((k_presum_seg<T, NPOL>), dim3(nblk(n_seg * 64, 256)), blk, 0, s,
+                       P->n_kept, P->gidx, P->group_start, P->order, vis, wt, dn, (cpx<T> *)A,
+                       (cpx<T> *)part);
+    hipLaunchKernelGGL((k_presum_join<T, NPOL>), dim3(nblk(P->n_groups, 256)), blk, 0, s,
+                       P->n_groups, P->group_start, dn, (const cpx<T> *)part, (cpx<T> *)A);
     return hipGetLastError();
 }
 
 hipError_t launch_presum_det(const lr_plan *P, const VisArgs &v, int precision, void *A,
-                             uint8_t *done, int64_t *counters, hipStream_t s) {
+                             uint8_t *done, void *part, int64_t *counters, hipStream_t s) {
     if (P->n_pairs == 0) return hipSuccess;
     const bool f64 = precision == LR_F64;
     switch (v.npol) {
-        case 1: return f64 ? presum_det_t<double, 1>(P, v, A, done, counters, s)
-                           : presum_det_t<float, 1>(P, v, A, done, counters, s);
-        case 2: return f64 ? presum_det_t<double, 2>(P, v, A, done, counters, s)
-                           : presum_det_t<float, 2>(P, v, A, done, counters, s);
-        default: return f64 ? presum_det_t<double, 4>(P, v, A, done, counters, s)
-                            : presum_det_t<float, 4>(P, v, A, done, counters, s);
+        case 1: return f64 ? presum_det_t<double, 1>(P, v, A, done, part, counters, s)
+                           : presum_det_t<float, 1>(P, v, A, done, part, counters, s);
+        case 2: return f64 ? presum_det_t<double, 2>(P, v, A, done, part, counters, s)
+                           : presum_det_t<float, 2>(P, v, A, done, part, counters, s);
+        default: return f64 ? presum_det_t<double, 4>(P, v, A, done, part, counters, s)
+                            : presum_det_t<float, 4>(P, v, A, done, part, counters, s);
     }
 }
 

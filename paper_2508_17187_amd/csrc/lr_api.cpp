@@ -374,6 +374,14 @@ static size_t det_bytes(int32_t nchan, int32_t npol) {
     return al256((size_t)std::max(nchan, 1) * kDetRowBlocks * npol * sizeof(double));
 }
 
+// Workspace of the deterministic group sums: one flag per group and the
+// pieces of groups that cross segment edges.
+static size_t det_group_bytes(int64_t n_groups, int64_t n_kept, int32_t npol, lr_precision precision) {
+    const int64_t n_seg = (std::max<int64_t>(n_kept, 1) + kDetSeg - 1) / kDetSeg;
+    return al256((size_t)std::max<int64_t>(n_groups, 1)) +
+           al256((size_t)n_seg * 2 * npol * (precision == LR_F64 ? 16 : 8));
+}
+
 // Resolve the plan of a call: the caller's, or a transient one at the start
 // of the workspace.  Returns the workspace bytes it used.
 lr_status resolve_plan(const lr_cf *cf, const lr_vis *v, int psf, void *work,
@@ -439,7 +447,9 @@ size_t lr_workspace_bytes(int op, const lr_cf_spec *spec, const lr_grid_spec *gr
         per = al256((size_t)std::max<int64_t>(n_groups, 1) * grid->npol * cplx_bytes(precision));
     // partial sums of weights and group flags of the deterministic mode
     if (op == LR_OP_GRID || op == LR_OP_SUMWT) per += det_bytes(vis->nchan, grid->npol);
-    if (op == LR_OP_GRID) per += al256((size_t)std::max<int64_t>(n_groups, 1));
+    if (op == LR_OP_GRID)
+        per += det_group_bytes(n_groups, vis->plan ? vis->plan->n_kept : n_pairs, grid->npol,
+                               precision);
     return plan + per + 256;
 }
 
@@ -698,7 +708,11 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
     // deterministic order (lr_set_deterministic): not for the PSF
     const bool det = g_det.load() != 0 && !psf;
     const size_t d_bytes =
-        det ? det_bytes(vis->nchan, vis->npol) + al256((size_t)std::max<int64_t>(ng_bound, 1)) : 0;
+        det ? det_bytes(vis->nchan, vis->npol) +
+                  det_group_bytes(ng_bound,
+                                  vis->plan ? vis->plan->n_kept : (int64_t)vis->nrow * vis->nchan,
+                                  vis->npol, precision)
+            : 0;
     if (work_bytes < plan_need + a_bytes + d_bytes)
         return fail(LR_E_WORKSPACE, "workspace needs %zu bytes, got %zu",
                     plan_need + a_bytes + d_bytes, work_bytes);
@@ -717,6 +731,7 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
         // weights from fixed partials, one workgroup per tile
         double *part = (double *)((char *)A + a_bytes);
         uint8_t *done = (uint8_t *)part + det_bytes(vis->nchan, vis->npol);
+        void *pieces = done + al256((size_t)std::max<int64_t>(ng_bound, 1));
         hipError_t e = launch_grid_setup(P, nullptr, 0, set ? sumwt : nullptr,
                                          sizeof(double) * cf->grid.nplane * vis->npol,
                                          set ? counters : nullptr, grid, precision, vis->npol,
@@ -724,7 +739,8 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
         if (e == hipSuccess && sumwt)
             e = launch_sumwt_det(P, vis->weight, precision, vis->npol, cf->grid.nplane, part,
                                  sumwt, s);
-        if (e == hipSuccess) e = launch_presum_det(P, va, precision, A, done, counters, s);
+        if (e == hipSuccess)
+            e = launch_presum_det(P, va, precision, A, done, pieces, counters, s);
         if (e == hipSuccess) {
             prof.begin();
             e = launch_grid(P, view_of(cf), A, grid, precision, vis->npol, cf->grid.nx,

@@ -121,12 +121,16 @@ hipError_t launch_rephase(void *vis, const double *uvw, const double *freq_hz,
 // Row blocks per channel of the deterministic sums of weights; the partials
 // take nchan * kDetRowBlocks * npol doubles of workspace.
 constexpr int kDetRowBlocks = 64;
+// Members per segment of the deterministic group sums; the pieces of groups
+// that cross segment edges take 2 * npol complex values per segment.
+constexpr int kDetSeg = 256;
 // Group sums in a fixed order, stored (no clear needed): with a row period
 // the column presum stores the groups it holds whole and flags them in
-// done[n_groups]; every other group is summed in the plan's sorted order.
+// done[n_groups]; every other group is summed over fixed segments of the
+// plan's sorted order, pieces in part[ceil(n_kept / kDetSeg)][2][npol].
 // Adds the sample counts to counters (if not null).
 hipError_t launch_presum_det(const lr_plan *P, const VisArgs &v, int precision, void *A,
-                             uint8_t *done, int64_t *counters, hipStream_t s);
+                             uint8_t *done, void *part, int64_t *counters, hipStream_t s);
 // sumwt[plane][pol] += sum of kept weights, in a fixed order.
 hipError_t launch_sumwt_det(const lr_plan *P, const void *weight, int precision, int32_t npol,
                             int32_t nplane, double *part, double *sumwt, hipStream_t s);

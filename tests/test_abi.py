@@ -165,8 +165,9 @@ def test_calibration_calls_validate_on_the_host(L):
 def test_deterministic_setting_and_its_workspace(L):
     """lr_set_deterministic is host-only and process-wide; the gridding
     workspace always has room for the deterministic mode's partial sums of
-    weights (nchan x 64 row blocks x npol doubles) and its one-byte group
-    flags, so a workspace sized once serves both modes."""
+    weights (nchan x 64 row blocks x npol doubles), its one-byte group flags
+    and the pieces of groups that cross 256-member segments (2 x npol complex
+    values per segment), so a workspace sized once serves both modes."""
     lib = L.lib()
     prev = lib.lr_deterministic()
     try:
@@ -180,4 +181,6 @@ def test_deterministic_setting_and_its_workspace(L):
     ws = {op: lib.lr_workspace_bytes(op, C.byref(s), C.byref(g), C.byref(v), L.LR_F32)
           for op in (L.LR_OP_GRID, L.LR_OP_DEGRID)}
     al = lambda n: (n + 255) // 256 * 256
-    assert ws[L.LR_OP_GRID] - ws[L.LR_OP_DEGRID] == al(nchan * 64 * npol * 8) + al(nrow * nchan)
+    n = nrow * nchan
+    assert ws[L.LR_OP_GRID] - ws[L.LR_OP_DEGRID] == (al(nchan * 64 * npol * 8) + al(n)
+                                                     + al((n + 255) // 256 * 2 * npol * 8))
