@@ -137,6 +137,15 @@ def _stream(stream=None):
     return C.c_void_p(s.cuda_stream)
 
 
+def _on_stream(t, stream):
+    """Tell torch's caching allocator that `t` is used by work on `stream`
+    (when it is not the current stream), so that its block is not handed to
+    other work before that stream's kernels are done with it."""
+    if t is not None and stream is not None and stream != torch.cuda.current_stream():
+        t.record_stream(stream)
+    return t
+
+
 def _vis_dtype(precision):
     return (torch.complex128, torch.float64) if precision == LR_F64 else (torch.complex64,
                                                                           torch.float32)
@@ -162,6 +171,8 @@ class CF:
             wb = L.lr_workspace_bytes(LR_OP_CF_BUILD, C.byref(self.spec), C.byref(self.grid),
                                       None, self.precision)
             work = torch.empty(max(wb, 1), dtype=torch.uint8, device=device)
+            _on_stream(self.blob, stream)
+            _on_stream(work, stream)
             _check(L.lr_cf_build(C.byref(self.spec), C.byref(self.grid), _ptr(self.blob),
                                  nbytes, _ptr(work), wb, _stream(stream),
                                  C.byref(self.handle)))
@@ -303,6 +314,7 @@ class Plan:
             self.buf = buf
         else:
             self.buf = torch.empty(n, dtype=torch.uint8, device=vis.uvw.device)
+        _on_stream(self.buf, stream)
         self.handle = C.c_void_p()
         self.cf = cf
         self.psf = bool(psf)
@@ -337,17 +349,17 @@ def workspace_bytes(op, cf, vis, precision):
     return lib().lr_workspace_bytes(op, C.byref(cf.spec), C.byref(cf.grid), C.byref(d), precision)
 
 
-def _work(op, cf, vis, precision, work):
+def _work(op, cf, vis, precision, work, stream=None):
     n = workspace_bytes(op, cf, vis, precision)
     if n == 0:
         raise LRError(LR_E_ARG, lib().lr_last_error().decode())
     if work is None or work.numel() < n:
         work = torch.empty(n, dtype=torch.uint8, device=vis.uvw.device)
-    return work
+    return _on_stream(work, stream)
 
 
 def lr_grid(cf, vis, precision, grid, sumwt=None, counters=None, work=None, stream=None):
-    work = _work(LR_OP_GRID, cf, vis, precision, work)
+    work = _work(LR_OP_GRID, cf, vis, precision, work, stream)
     d = vis.desc()
     _check(lib().lr_grid(cf.handle, C.byref(d), precision, _ptr(grid), _ptr(sumwt),
                          _ptr(counters), _ptr(work), work.numel(), _stream(stream)))
@@ -356,7 +368,7 @@ def lr_grid(cf, vis, precision, grid, sumwt=None, counters=None, work=None, stre
 
 def lr_grid_overwrite(cf, vis, precision, grid, sumwt=None, counters=None, work=None,
                       stream=None):
-    work = _work(LR_OP_GRID, cf, vis, precision, work)
+    work = _work(LR_OP_GRID, cf, vis, precision, work, stream)
     d = vis.desc()
     _check(lib().lr_grid_overwrite(cf.handle, C.byref(d), precision, _ptr(grid), _ptr(sumwt),
                                    _ptr(counters), _ptr(work), work.numel(), _stream(stream)))
@@ -364,7 +376,7 @@ def lr_grid_overwrite(cf, vis, precision, grid, sumwt=None, counters=None, work=
 
 
 def lr_degrid(cf, vis, precision, grid, counters=None, work=None, stream=None):
-    work = _work(LR_OP_DEGRID, cf, vis, precision, work)
+    work = _work(LR_OP_DEGRID, cf, vis, precision, work, stream)
     d = vis.desc()
     _check(lib().lr_degrid(cf.handle, C.byref(d), precision, _ptr(grid), _ptr(counters),
                            _ptr(work), work.numel(), _stream(stream)))
@@ -373,7 +385,7 @@ def lr_degrid(cf, vis, precision, grid, counters=None, work=None, stream=None):
 
 def lr_make_psf(cf, vis, precision, psf_grid, sumwt=None, counters=None, work=None,
                 stream=None):
-    work = _work(LR_OP_PSF, cf, vis, precision, work)
+    work = _work(LR_OP_PSF, cf, vis, precision, work, stream)
     d = vis.desc()
     _check(lib().lr_make_psf(cf.handle, C.byref(d), precision, _ptr(psf_grid), _ptr(sumwt),
                              _ptr(counters), _ptr(work), work.numel(), _stream(stream)))
@@ -381,7 +393,7 @@ def lr_make_psf(cf, vis, precision, psf_grid, sumwt=None, counters=None, work=No
 
 
 def lr_sumwt(cf, vis, precision, sumwt, counters=None, work=None, stream=None):
-    work = _work(LR_OP_SUMWT, cf, vis, precision, work)
+    work = _work(LR_OP_SUMWT, cf, vis, precision, work, stream)
     d = vis.desc()
     _check(lib().lr_sumwt(cf.handle, C.byref(d), precision, _ptr(sumwt), _ptr(counters),
                           _ptr(work), work.numel(), _stream(stream)))

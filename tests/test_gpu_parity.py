@@ -129,10 +129,7 @@ def test_map_bitexact_config1():
 
 # --- CF tables ----------------------------------------------------------------------
 
-@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
-def test_cf_table_matches_oracle(awp, form):
-    wl, ocf = awp
-    say("cf", form)
+def check_cf_table(wl, ocf, form):
     cf = W.build_cf(wl, PREC[form])
     got = cf.table_host()
     ref = ocf.table
@@ -157,6 +154,13 @@ def test_cf_table_matches_oracle(awp, form):
     assert np.all(diff <= ulp * np.abs(ref) * 1.01 + 2 * sub + 1e-12 * scale)
 
 
+@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
+def test_cf_table_matches_oracle(awp, form):
+    wl, ocf = awp
+    say("cf", form)
+    check_cf_table(wl, ocf, form)
+
+
 # --- gridding, degridding, PSF --------------------------------------------------------
 
 def run_grid(wl, form, plan=False, pointing=None):
@@ -173,10 +177,7 @@ def run_grid(wl, form, plan=False, pointing=None):
     return g.cpu().numpy(), sw.cpu().numpy(), cnt.cpu().numpy()
 
 
-@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
-def test_grid_parity(awp, form):
-    wl, ocf = awp
-    say("grid", form)
+def check_grid(wl, ocf, form):
     g, sw, cnt = run_grid(wl, form)
     pr = Problem.from_workload(wl, ocf)
     ref = pr.grid(wl.vis, wl.weight)
@@ -187,6 +188,13 @@ def test_grid_parity(awp, form):
     assert np.array_equal(cnt, c_ref)
     assert np.max(np.abs(sw - s_ref) / np.abs(s_ref).max()) < 1e-12
     assert c_ref[0] > 0 and c_ref[1] > 0 and c_ref[2] > 0
+
+
+@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
+def test_grid_parity(awp, form):
+    wl, ocf = awp
+    say("grid", form)
+    check_grid(wl, ocf, form)
 
 
 def test_rows_in_any_order(awp):
@@ -225,10 +233,7 @@ def test_grid_with_plan_equals_transient_plan(awp):
     assert np.array_equal(ca, cb) and np.allclose(sa, sb, rtol=1e-15, atol=0)
 
 
-@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
-def test_degrid_parity(awp, form):
-    wl, ocf = awp
-    say("degrid", form)
+def check_degrid(wl, ocf, form):
     p = PREC[form]
     rng = np.random.default_rng(5)
     shape = (wl.grid.nplane, wl.grid.npol, wl.grid.ny, wl.grid.nx)
@@ -248,6 +253,51 @@ def test_degrid_parity(awp, form):
     assert e <= TOL[form]
     assert np.all(got[ref == 0] == 0)
     assert np.array_equal(cnt.cpu().numpy(), pr.sumwt(wl.weight)[1])
+
+
+@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
+def test_degrid_parity(awp, form):
+    wl, ocf = awp
+    say("degrid", form)
+    check_degrid(wl, ocf, form)
+
+
+# --- every row of Table AWP-CFSETUP -------------------------------------------------
+# The kernel compositions of the table: PS*A*W, A*W, PS*A (A-Projection),
+# A alone and W without the PS taper are the PSTerm-off rows, PS*W
+# (W-Projection) and PS alone (Standard).
+
+TERM_ROWS = {"PSxAxW": TERM_PS | TERM_A | TERM_W, "AxW": TERM_A | TERM_W,
+             "PSxA": TERM_PS | TERM_A, "A": TERM_A, "PSxW": TERM_PS | TERM_W, "PS": TERM_PS}
+
+
+@pytest.fixture(scope="module", params=list(TERM_ROWS), ids=list(TERM_ROWS))
+def awp_row(request):
+    import dataclasses
+    wl = awp_workload(seed_id=93, h_max=7)
+    wl.cf = dataclasses.replace(wl.cf, terms=TERM_ROWS[request.param])
+    return wl, oracle.build_cf(wl.grid, wl.cf)
+
+
+@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
+def test_cf_table_every_row(awp_row, form):
+    wl, ocf = awp_row
+    say("cf row", wl.cf.terms, form)
+    check_cf_table(wl, ocf, form)
+
+
+@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
+def test_grid_parity_every_row(awp_row, form):
+    wl, ocf = awp_row
+    say("grid row", wl.cf.terms, form)
+    check_grid(wl, ocf, form)
+
+
+@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
+def test_degrid_parity_every_row(awp_row, form):
+    wl, ocf = awp_row
+    say("degrid row", wl.cf.terms, form)
+    check_degrid(wl, ocf, form)
 
 
 @pytest.mark.parametrize("form", ["f64", "f32", "f16cf"])

@@ -188,3 +188,129 @@ def test_compact_table_holds_the_same_planes_and_guards_the_rest():
                                                  compact=True))
     assert np.array_equal(pr_full.grid(wl.vis, wl.weight),
                           Problem.from_workload(wl, full).grid(wl.vis, wl.weight))
+
+
+# --- sign of the W term ---------------------------------------------------------
+#
+# Eq. ME (with the F sign of the conventions) gives a sample of a unit point
+# source at (l0, m0) the phase exp(-2 pi i (u l0 + v m0 + w (n0 - 1))),
+# n = sqrt(1 - l^2 - m^2).  Degridding D predicts a sample from F of the
+# model image, and gridding G = D^H; for W-projection to remove the w-phase,
+# the image-plane response of a gridded sample on w-plane k must carry
+# exp(+2 pi i w_k (n - 1)) relative to the w = 0 plane, and degridding must
+# reproduce the direct sum above for either sign of w.  Both checks below
+# fail by O(1) when the screen's W sign is flipped (planted in the oracle by
+# swapping its screen for one evaluated at -w_k).
+
+def _wproj_setup(O=20, n_w=3, w_max=6000.0):
+    nx = 64
+    cell = 120.0 * synth.ARCSEC
+    g = synth.GridSetup(nx, nx, 1, 1, cell, cell)
+    cf = synth.CFSetup(terms=TERM_PS | TERM_W, oversample=O, ps_support=7, n_w=n_w,
+                       w_max=w_max, h_min=4, h_max=10, fg_hz=np.array([3e9]))
+    return g, cf
+
+
+def _flipped_w_screen(monkeypatch):
+    import oracle.cfbuild as cfb
+    orig = cfb.screen
+
+    def flipped(M, nx, ny, cell_l, cell_m, terms, ps_support, w_k, *a, **kw):
+        return orig(M, nx, ny, cell_l, cell_m, terms, ps_support, -w_k, *a, **kw)
+
+    monkeypatch.setattr(cfb, "screen", flipped)
+
+
+def _plane_response(g, cf, ocf, k, p=(34, 29), nu=3e9):
+    """F^dagger of the grid of one unit sample at the lattice point p (offset
+    0) with w exactly on plane k."""
+    from oracle.imaging import centred_ifft
+    from oracle.native import Problem
+    du = 1.0 / (g.nx * g.cell_l)
+    lam = synth.C_LIGHT / nu
+    w = k * cf.w_max / (cf.n_w - 1)
+    uvw = np.array([[(p[0] - g.nx // 2) * du * lam, (p[1] - g.ny // 2) * du * lam, w * lam]])
+    pr = Problem(uvw, np.array([nu]), np.zeros(1, np.int32), np.zeros(1, np.int32), g.nx, g.ny,
+                 1, 1, g.cell_l, g.cell_m, ocf)
+    m = pr.map()[0, 0]
+    assert m[6] == 1 and m[2] == 0 and m[3] == 0 and m[4] == k
+    return centred_ifft(pr.grid(np.ones((1, 1, 1), complex), np.ones((1, 1, 1)))[0, 0])
+
+
+def _w_phase_deviation(g, cf, ocf):
+    ix = np.arange(g.nx) - g.nx // 2
+    ll, mm = np.meshgrid(ix * g.cell_l, ix * g.cell_m)
+    n1 = np.sqrt(1.0 - ll * ll - mm * mm) - 1.0
+    inner = (np.abs(ix)[None, :] < g.nx // 4) & (np.abs(ix)[:, None] < g.nx // 4)
+    r0 = _plane_response(g, cf, ocf, 0)
+    out = []
+    for k in range(1, cf.n_w):
+        wk = k * cf.w_max / (cf.n_w - 1)
+        want = np.exp(2j * np.pi * wk * n1)
+        out.append((np.abs(wk * n1[inner]).max(),
+                    np.abs(_plane_response(g, cf, ocf, k) / r0 - want)[inner].max()))
+    return out
+
+
+def test_w_term_sign_image_plane_response():
+    g, cf = _wproj_setup()
+    dev = _w_phase_deviation(g, cf, build_cf(g, cf))
+    # the w-phase reaches a quarter turn and more over the inner half
+    assert dev[-1][0] > 0.4
+    for _, d in dev:
+        assert d < 2e-3
+
+
+def test_w_term_sign_flipped_screen_fails_image_plane_pin(monkeypatch):
+    g, cf = _wproj_setup()
+    _flipped_w_screen(monkeypatch)
+    dev = _w_phase_deviation(g, cf, build_cf(g, cf))
+    assert max(d for _, d in dev) > 1.0
+
+
+def _predict_point_source(g, cf, ocf, nsamp=400, seed=3):
+    """Degrid the centred FFT of a unit point source (divided by the PS grid
+    correction of plane 0) at random (u, v) with w on planes of either sign;
+    return (prediction, direct sum of Eq. ME, pixel offsets of the source)."""
+    from oracle.imaging import centred_fft, gcf_1d, separable_1d
+    from oracle.native import Problem
+    nx, O = g.nx, cf.oversample
+    gc = gcf_1d(separable_1d(ocf, k=0), O, nx).real
+    dx, dy = 12, -10
+    l0, m0 = dx * g.cell_l, dy * g.cell_m
+    n0 = np.sqrt(1.0 - l0 * l0 - m0 * m0) - 1.0
+    img = np.zeros((nx, nx))
+    img[nx // 2 + dy, nx // 2 + dx] = 1.0
+    grid = centred_fft(img / np.outer(gc, gc))[None, None]
+    rng = np.random.default_rng(seed)
+    nu = 3e9
+    lam = synth.C_LIGHT / nu
+    du = 1.0 / (nx * g.cell_l)
+    u = rng.uniform(-18, 18, nsamp) * du
+    v = rng.uniform(-18, 18, nsamp) * du
+    w = np.where(rng.random(nsamp) < 0.5, -1.0, 1.0) * rng.integers(0, cf.n_w, nsamp) * (
+        cf.w_max / (cf.n_w - 1))
+    pr = Problem(np.stack([u, v, w], 1) * lam, np.array([nu]), np.zeros(1, np.int32),
+                 np.zeros(1, np.int32), nx, nx, 1, 1, g.cell_l, g.cell_m, ocf)
+    assert pr.map()[..., 6].all()
+    got = pr.degrid(grid)[:, 0, 0]
+    want = np.exp(-2j * np.pi * (u * l0 + v * m0 + w * n0))
+    return got, want, (dx, dy), np.abs(w * n0).max()
+
+
+def test_w_projection_predicts_the_direct_sum_for_both_signs_of_w():
+    g, cf = _wproj_setup(O=40, n_w=5)
+    got, want, (dx, dy), wn = _predict_point_source(g, cf, build_cf(g, cf))
+    assert wn > 0.2
+    # offsets quantise u, v to 1/O of a cell: phase error <= pi (|dx| + |dy|)
+    # / (nx O); the kernel truncation adds ~1e-3
+    bound = np.pi * (abs(dx) + abs(dy)) / (g.nx * cf.oversample) + 5e-3
+    assert np.abs(got - want).max() < bound
+    assert np.sqrt(np.mean(np.abs(got - want) ** 2)) < 0.5 * bound
+
+
+def test_w_projection_prediction_fails_with_flipped_screen(monkeypatch):
+    g, cf = _wproj_setup(O=40, n_w=5)
+    _flipped_w_screen(monkeypatch)
+    got, want, _, _ = _predict_point_source(g, cf, build_cf(g, cf))
+    assert np.sqrt(np.mean(np.abs(got - want) ** 2)) > 0.5
