@@ -192,6 +192,23 @@ lr_status lr_plan_build(const lr_cf *cf, const lr_vis *vis, int psf, void *buf,
 
 void lr_plan_free(lr_plan *plan);
 
+/* Bytes a built plan's arrays take at their actual sizes.  lr_plan_build
+ * needs a buffer sized for the worst case (lr_plan_bytes, several times
+ * larger for wide supports) that also holds the build's transient arrays;
+ * packing moves what the plan keeps into a buffer of this size, so that
+ * many plans (one per chunk of a large data set) can stay resident.  0 for
+ * a NULL plan. */
+size_t lr_plan_packed_bytes(const lr_plan *plan);
+
+/* Copy plan's arrays into buf (device, >= lr_plan_packed_bytes) on stream
+ * and return a new handle over buf in *out, usable exactly as the original
+ * (same results, bit for bit).  The original buffer may be reused or freed
+ * once the copies have run on the stream; the original handle stays valid
+ * while its buffer lives.  Release the new handle with lr_plan_free.
+ * LR_E_WORKSPACE when buf is too small. */
+lr_status lr_plan_pack(const lr_plan *plan, void *buf, size_t bytes, lr_stream stream,
+                       lr_plan **out);
+
 /* Number of groups, kept (row, channel) pairs and total pairs of a plan,
  * and the kernel taps its groups cover, sum over groups of S_k^2 (the
  * gridder and degridder each do one complex multiply-add per tap and

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "lr_internal.h"
@@ -549,6 +550,81 @@ lr_status lr_plan_build(const lr_cf *cf, const lr_vis *vis, int psf, void *buf, 
 
 void lr_plan_free(lr_plan *plan) { delete plan; }
 
+namespace {
+// The arrays a built plan keeps, at their actual sizes (the build buffer is
+// sized for the worst case and also holds the build's transient arrays).
+struct PackedLayout {
+    size_t chan, order, gidx, pair_group, group_start, groups, tp_group, chunk_start,
+        chunk_tile, chunk_excl, chunk_order, tile_state, shared_tiles, total;
+};
+
+PackedLayout packed_layout(const lr_plan *P) {
+    PackedLayout L;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off += al256(bytes); return o; };
+    L.chan = take(sizeof(ChanConst) * std::max<int32_t>(P->nchan, 1));
+    L.order = take(sizeof(int32_t) * P->n_pairs);
+    L.gidx = take(sizeof(int32_t) * P->n_kept);
+    L.pair_group = take(sizeof(int32_t) * P->n_pairs);
+    L.group_start = take(sizeof(int32_t) * (P->n_groups + 1));
+    L.groups = take(sizeof(GroupMeta) * P->n_groups);
+    L.tp_group = take(sizeof(int32_t) * P->n_tile_pairs);
+    L.chunk_start = take(sizeof(int32_t) * (P->n_chunks + 1));
+    L.chunk_tile = take(sizeof(int32_t) * P->n_chunks);
+    L.chunk_excl = take(sizeof(int32_t) * P->n_chunks);
+    L.chunk_order = take(P->chunk_order ? sizeof(int32_t) * P->n_chunks : 0);
+    L.tile_state = take(sizeof(int32_t) * P->n_tiles);
+    L.shared_tiles = take(sizeof(int32_t) * P->n_shared);
+    L.total = off;
+    return L;
+}
+}  // namespace
+
+size_t lr_plan_packed_bytes(const lr_plan *plan) {
+    if (!plan) { fail(LR_E_ARG, "plan is NULL"); return 0; }
+    return packed_layout(plan).total;
+}
+
+lr_status lr_plan_pack(const lr_plan *plan, void *buf, size_t bytes, lr_stream stream,
+                       lr_plan **out) {
+    if (!out) return fail(LR_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!plan) return fail(LR_E_ARG, "plan is NULL");
+    const PackedLayout L = packed_layout(plan);
+    if (!buf) return fail(LR_E_ARG, "buf is NULL");
+    if (bytes < L.total) return fail(LR_E_WORKSPACE, "packed plan needs %zu bytes, got %zu", L.total, bytes);
+    lr_plan *Q = new (std::nothrow) lr_plan(*plan);
+    if (!Q) return fail(LR_E_ARG, "out of host memory");
+    hipStream_t s = (hipStream_t)stream;
+    char *b = (char *)buf;
+    hipError_t e = hipSuccess;
+    auto move = [&](auto *&dst, const void *src, size_t off, size_t n_bytes) {
+        using Ptr = typename std::remove_reference<decltype(dst)>::type;
+        dst = (Ptr)(b + off);
+        if (e == hipSuccess && n_bytes)
+            e = hipMemcpyAsync(b + off, src, n_bytes, hipMemcpyDeviceToDevice, s);
+    };
+    const lr_plan *P = plan;
+    move(Q->cc, P->cc, L.chan, sizeof(ChanConst) * P->nchan);
+    move(Q->order, P->order, L.order, sizeof(int32_t) * P->n_pairs);
+    move(Q->gidx, P->gidx, L.gidx, sizeof(int32_t) * P->n_kept);
+    move(Q->pair_group, P->pair_group, L.pair_group, sizeof(int32_t) * P->n_pairs);
+    move(Q->group_start, P->group_start, L.group_start, sizeof(int32_t) * (P->n_groups + 1));
+    move(Q->groups, P->groups, L.groups, sizeof(GroupMeta) * P->n_groups);
+    move(Q->tp_group, P->tp_group, L.tp_group, sizeof(int32_t) * P->n_tile_pairs);
+    move(Q->chunk_start, P->chunk_start, L.chunk_start, sizeof(int32_t) * (P->n_chunks + 1));
+    move(Q->chunk_tile, P->chunk_tile, L.chunk_tile, sizeof(int32_t) * P->n_chunks);
+    move(Q->chunk_excl, P->chunk_excl, L.chunk_excl, sizeof(int32_t) * P->n_chunks);
+    if (P->chunk_order)
+        move(Q->chunk_order, P->chunk_order, L.chunk_order, sizeof(int32_t) * P->n_chunks);
+    move(Q->tile_state, P->tile_state, L.tile_state, sizeof(int32_t) * P->n_tiles);
+    move(Q->shared_tiles, P->shared_tiles, L.shared_tiles, sizeof(int32_t) * P->n_shared);
+    Q->bytes_used = L.total;
+    if (e != hipSuccess) { delete Q; return dev_fail(e, "plan pack"); }
+    *out = Q;
+    return LR_OK;
+}
+
 lr_status lr_gcf(const lr_cf *cf, int32_t fg, int32_t k, int32_t n, void *out,
                  lr_stream stream) {
     if (!cf || !out) return fail(LR_E_ARG, "NULL argument");
@@ -691,6 +767,22 @@ lr_status lr_set_profile_events(void *start, void *stop) {
     return LR_OK;
 }
 
+// Scratch of a gridding call beyond a transient plan: the group sums and,
+// in the deterministic order, its partial sums.  a_bytes receives the
+// group-sum part.
+static size_t grid_scratch_bytes(const lr_vis *vis, lr_precision precision, bool det,
+                                 size_t &a_bytes) {
+    int64_t ng_bound = vis->plan ? vis->plan->n_groups : (int64_t)vis->nrow * vis->nchan;
+    a_bytes = al256((size_t)std::max<int64_t>(ng_bound, 1) * vis->npol * cplx_bytes(precision));
+    const size_t d_bytes =
+        det ? det_bytes(vis->nchan, vis->npol) +
+                  det_group_bytes(ng_bound,
+                                  vis->plan ? vis->plan->n_kept : (int64_t)vis->nrow * vis->nchan,
+                                  vis->npol, precision)
+            : 0;
+    return a_bytes + d_bytes;
+}
+
 static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
                              void *grid, double *sumwt, int64_t *counters, void *work,
                              size_t work_bytes, lr_stream stream, int mode) {
@@ -703,19 +795,14 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
     hipStream_t s = (hipStream_t)stream;
     // size check of the per-call scratch before anything is enqueued
     int64_t ng_bound = vis->plan ? vis->plan->n_groups : (int64_t)vis->nrow * vis->nchan;
-    size_t a_bytes = al256((size_t)std::max<int64_t>(ng_bound, 1) * vis->npol * cplx_bytes(precision));
     size_t plan_need = vis->plan ? 0 : al256(plan_total(cf, vis));
     // deterministic order (lr_set_deterministic): not for the PSF
     const bool det = g_det.load() != 0 && !psf;
-    const size_t d_bytes =
-        det ? det_bytes(vis->nchan, vis->npol) +
-                  det_group_bytes(ng_bound,
-                                  vis->plan ? vis->plan->n_kept : (int64_t)vis->nrow * vis->nchan,
-                                  vis->npol, precision)
-            : 0;
-    if (work_bytes < plan_need + a_bytes + d_bytes)
+    size_t a_bytes = 0;
+    const size_t scratch_need = grid_scratch_bytes(vis, precision, det, a_bytes);
+    if (work_bytes < plan_need + scratch_need)
         return fail(LR_E_WORKSPACE, "workspace needs %zu bytes, got %zu",
-                    plan_need + a_bytes + d_bytes, work_bytes);
+                    plan_need + scratch_need, work_bytes);
     lr_plan tmp;
     const lr_plan *P = nullptr;
     size_t used = 0;

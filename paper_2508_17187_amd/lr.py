@@ -68,6 +68,8 @@ EXPORTS = {
     "lr_plan_build": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
                                 C.c_void_p, C.c_void_p]),
     "lr_plan_free": (None, [C.c_void_p]),
+    "lr_plan_packed_bytes": (C.c_size_t, [C.c_void_p]),
+    "lr_plan_pack": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_void_p]),
     "lr_plan_info": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lr_set_profile_events": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lr_set_deterministic": (C.c_int, [C.c_int32]),
@@ -320,6 +322,22 @@ class Plan:
         self.psf = bool(psf)
         _check(L.lr_plan_build(cf.handle, C.byref(d), int(psf), _ptr(self.buf), n,
                                _stream(stream), C.byref(self.handle)))
+
+    def packed(self, stream=None):
+        """A copy of this plan in a buffer of its actual size
+        (lr_plan_pack); this plan's buffer may be dropped afterwards."""
+        L = lib()
+        n = L.lr_plan_packed_bytes(self.handle)
+        if n == 0:
+            raise LRError(LR_E_ARG, L.lr_last_error().decode())
+        q = Plan.__new__(Plan)
+        q.buf = torch.empty(n, dtype=torch.uint8, device=self.buf.device)
+        _on_stream(q.buf, stream)
+        _on_stream(self.buf, stream)
+        q.handle = C.c_void_p()
+        q.cf, q.psf = self.cf, self.psf
+        _check(L.lr_plan_pack(self.handle, _ptr(q.buf), n, _stream(stream), C.byref(q.handle)))
+        return q
 
     def info(self):
         a, b, c, d = C.c_int64(), C.c_int64(), C.c_int64(), C.c_int64()
