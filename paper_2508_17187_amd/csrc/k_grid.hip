@@ -391,8 +391,10 @@ __global__ __launch_bounds__(256) void k_presum(
 // shuffle reduces along the steps, and the open run of each column is
 // carried from the last step of a block to the first step of the next.
 // A finished run is added to A with an atomic, or simply stored when it is
-// a whole group: a single-run group (kSingleRun) whose run neither began
-// before this wavefront's first step nor continues past its last one.
+// a whole group: a one-member group (kSingleton), or a single-run group
+// (kSingleRun) whose run neither began before this wavefront's first step
+// nor continues past its last one.  Only the groups with more than one
+// member therefore need a cleared start.
 // DET (deterministic order) stores those groups and sets done[g], and adds
 // nothing with atomics: the other groups are summed again afterwards, in a
 // fixed order, by k_presum_seg and k_presum_join.
@@ -419,7 +421,7 @@ __global__ __launch_bounds__(256) void k_presum_col(
         carry[p] = {(T)0, (T)0};
     }
     int carry_g = -1, plane = -1;
-    bool carry_single = false;
+    bool carry_single = false, carry_alone = false;
     // the run holding this wavefront's first step of my column may have
     // begun in the previous wavefront: it is never stored, only added
     bool open0 = false;
@@ -467,7 +469,9 @@ __global__ __launch_bounds__(256) void k_presum_col(
         cpx<T> a[NPOL];
         for (int p = 0; p < NPOL; ++p) a[p] = {(T)0, (T)0};
         const bool single = cur.g >= 0 && (cur.g & kSingleRun);
-        const int g = cur.g >= 0 ? (cur.g & ~kSingleRun) : cur.g;
+        // a one-member group's run is always whole: its sum is stored
+        const bool alone = cur.g >= 0 && (cur.g & kSingleton);
+        const int g = cur.g >= 0 ? (cur.g & ~kGroupFlags) : cur.g;
         if (cur.valid) {
             // the channel, hence the plane, of a lane's column is fixed
             if (g >= 0 && plane < 0) plane = groups[g].plane;
@@ -504,7 +508,7 @@ __global__ __launch_bounds__(256) void k_presum_col(
                 }
             } else {
                 carry_ended = true;
-                emit(carry_g, carry_single && !open0, carry);
+                emit(carry_g, (carry_single && !open0) || carry_alone, carry);
             }
         }
         const bool col_carry_ended = __shfl(carry_ended, cl);
@@ -525,20 +529,21 @@ __global__ __launch_bounds__(256) void k_presum_col(
         const uint64_t endmask = __ballot(ends);
         if (ends) {
             const bool first = open0 && !col_carry_ended && !(endmask & below);
-            emit(g, single && !first, a);
+            emit(g, (single && !first) || alone, a);
         }
         if (col_carry_ended || (endmask & colmask)) open0 = false;
         // hand the last step's run to the first step of the next block
         const int src = (lane & (kColW - 1)) + (kColT - 1) * kColW;
         carry_g = __shfl(g, src);
         carry_single = __shfl(single, src);
+        carry_alone = __shfl(alone, src);
         for (int p = 0; p < NPOL; ++p) {
             carry[p].x = __shfl(a[p].x, src);
             carry[p].y = __shfl(a[p].y, src);
         }
     }
     // the run still open may continue in the next wavefront
-    if (SUMS && tl == 0 && carry_g >= 0) emit(carry_g, false, carry);
+    if (SUMS && tl == 0 && carry_g >= 0) emit(carry_g, carry_alone, carry);
     if (counters) {
         kept = wave_sum_ll(kept);
         flagged = wave_sum_ll(flagged);
@@ -837,6 +842,12 @@ struct SetupArgs {
     int32_t n_shared, ntx, nty, nx, ny;
     int64_t pol_stride;
     void *grid;
+    // group sums cleared by list (instead of span 0): the groups in multi
+    uint64_t *A;
+    const int32_t *multi;
+    int64_t n_multi;
+    int32_t gwords;           // words per group sum
+    int32_t multi_blocks;
 };
 
 template <typename T, int NPOL>
@@ -846,7 +857,16 @@ __global__ __launch_bounds__(256) void k_grid_setup(SetupArgs a) {
                             (cpx<T> *)a.grid);
         return;
     }
-    int64_t w = ((int64_t)(blockIdx.x - a.n_shared) * blockDim.x + threadIdx.x) * 4;
+    const int b = (int)blockIdx.x - a.n_shared;
+    if (b < a.multi_blocks) {
+        const int64_t i = (int64_t)b * blockDim.x + threadIdx.x;
+        if (i < a.n_multi) {
+            uint64_t *q = a.A + (int64_t)a.multi[i] * a.gwords;
+            for (int w = 0; w < a.gwords; ++w) q[w] = 0;
+        }
+        return;
+    }
+    int64_t w = ((int64_t)(b - a.multi_blocks) * blockDim.x + threadIdx.x) * 4;
     for (int i = 0; i < 4; ++i, ++w) {
         int64_t r = w;
         for (int k = 0; k < 3; ++k) {
@@ -1041,7 +1061,7 @@ __global__ __launch_bounds__(256) void k_expand(int64_t n_pairs, const int32_t *
     const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n_pairs) return;
     int g = pair_group[j];
-    if (g >= 0) g &= ~kSingleRun;
+    if (g >= 0) g &= ~kGroupFlags;
     cpx<T> out[NPOL];
     T w[NPOL];
     if (weight) sload(weight + j * NPOL, w);
@@ -1343,8 +1363,16 @@ hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *
                              int precision, int32_t npol, int32_t nx, int32_t ny, bool set,
                              hipStream_t s) {
     SetupArgs sa;
+    // with a row period the track presum stores the sums of one-member
+    // groups, so only the other groups are cleared
+    const bool by_list = A && P->period > 0;
+    sa.A = (uint64_t *)A;
+    sa.multi = P->multi;
+    sa.n_multi = by_list ? P->n_multi : 0;
+    sa.gwords = npol * (precision == LR_F64 ? 2 : 1);
+    sa.multi_blocks = (int32_t)((sa.n_multi + 255) / 256);
     sa.z[0] = (uint64_t *)A;
-    sa.zw[0] = A ? (int64_t)(a_bytes / 8) : 0;
+    sa.zw[0] = A && !by_list ? (int64_t)(a_bytes / 8) : 0;
     sa.z[1] = (uint64_t *)sumwt;
     sa.zw[1] = sumwt ? (int64_t)(sumwt_bytes / 8) : 0;
     sa.z[2] = (uint64_t *)counters;
@@ -1358,7 +1386,7 @@ hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *
     sa.pol_stride = (int64_t)nx * ny;
     sa.grid = grid;
     const int64_t words = sa.zw[0] + sa.zw[1] + sa.zw[2];
-    const int64_t n_blocks = sa.n_shared + (words + 1023) / 1024;
+    const int64_t n_blocks = sa.n_shared + sa.multi_blocks + (words + 1023) / 1024;
     if (n_blocks == 0) return hipSuccess;
     const bool f64 = precision == LR_F64;
     switch (npol) {

@@ -157,7 +157,7 @@ __global__ void k_group_meta(const int32_t *vals, const int32_t *flags, const in
                              const ChanConst *cc, MapGeom g, CFView cf,
                              const int32_t *ant1, const int32_t *ant2,
                              const double *ant_dlm, double du_dl, double dv_dm,
-                             int32_t *group_start, GroupMeta *groups) {
+                             int32_t *group_start, GroupMeta *groups, int64_t *geo) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_kept || !flags[i]) return;
     int32_t gi = gidx[i];
@@ -199,6 +199,8 @@ __global__ void k_group_meta(const int32_t *vals, const int32_t *flags, const in
         gm.bv = (dv_dm * dm) / (double)g.O;
     }
     groups[gi] = gm;
+    geo[gi] = (int64_t)(uint16_t)m.pu | ((int64_t)(uint16_t)m.pv << 16) |
+              ((int64_t)(uint16_t)(int16_t)m.ou << 32) | ((int64_t)(uint16_t)(int16_t)m.ov << 48);
 }
 
 // The exclusive scan counts a group's own start for every later pair of the
@@ -367,8 +369,34 @@ __global__ void k_single_gaps(const int32_t *order, const int32_t *gidx, int64_t
     if ((int64_t)order[i] - order[i - 1] != period) single[gidx[i]] = 0;
 }
 
+// One-member groups (bit 1 of single[g]; the presum stores their sums, which
+// never need a cleared start) and the list of the other groups, which the
+// presum may add to with atomics (any order).
+__global__ void k_group_kinds(const int32_t *group_start, int64_t n_groups, int32_t *single,
+                              int32_t *multi, int32_t *count) {
+    int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= n_groups) return;
+    if (group_start[g + 1] - group_start[g] == 1) single[g] |= 2;
+    else multi[atomicAdd(count, 1)] = (int32_t)g;
+}
+
+// First (tile, group) pair of every tile in the tile-sorted pair list
+// (keys), by binary search; tile_tp[n_tiles] = n.
+__global__ void k_tile_ranges(const uint32_t *keys, int64_t n, int64_t n_tiles,
+                              int32_t *tile_tp) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t > n_tiles) return;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+        int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)keys[mid] < t) lo = mid + 1; else hi = mid;
+    }
+    tile_tp[t] = (int32_t)lo;
+}
+
 // Group of every pair in natural (row, channel) order: >= 0 kept (bit
-// kSingleRun set for a single-run group), -1 dropped, -2 skipped channel.
+// kSingleRun set for a single-run group, kSingleton for a one-member
+// group), -1 dropped, -2 skipped channel.
 __global__ void k_pair_group(const int32_t *order, const int32_t *gidx, const int32_t *single,
                              int64_t n_kept, int64_t n_pairs, int32_t *pair_group) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -378,7 +406,8 @@ __global__ void k_pair_group(const int32_t *order, const int32_t *gidx, const in
     int32_t out = ((v >> 30) & 1) ? -2 : -1;
     if (i < n_kept) {
         const int32_t g = gidx[i];
-        out = g | (single && single[g] ? kSingleRun : 0);
+        const int32_t k = single ? single[g] : 0;
+        out = g | ((k & 1) ? kSingleRun : 0) | ((k & 2) ? kSingleton : 0);
     }
     pair_group[pair] = out;
 }
@@ -460,6 +489,9 @@ PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max, int64_t n_
     L.chunk_order = take(sizeof(int32_t) * ntp);
     L.tile_state = take(sizeof(int32_t) * std::max<int64_t>(n_tiles, 1));
     L.shared_tiles = take(sizeof(int32_t) * std::max<int64_t>(n_tiles, 1));
+    L.geo = take(sizeof(int64_t) * n);
+    L.tile_tp = take(sizeof(int32_t) * (std::max<int64_t>(n_tiles, 1) + 1));
+    L.multi = take(sizeof(int32_t) * n);
     L.persistent = off;
     // transient
     L.keys_a = take(sizeof(uint64_t) * std::max(n, ntp));
@@ -506,9 +538,15 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->n_tiles = tile_count(g.nx, g.ny, g.nplane);
     P->shared_tiles = (int32_t *)(buf + L.shared_tiles);
     P->n_shared = 0;
+    P->geo = (int64_t *)(buf + L.geo);
+    P->tile_tp = (int32_t *)(buf + L.tile_tp);
+    P->multi = (int32_t *)(buf + L.multi);
+    P->n_multi = 0;
     P->cc = d_cc;
     P->n_kept = P->n_groups = P->n_tile_pairs = P->n_chunks = P->taps = 0;
     if ((e = launch_zero(P->tile_state, sizeof(int32_t) * P->n_tiles, s)) != hipSuccess)
+        return e;
+    if ((e = launch_zero(P->tile_tp, sizeof(int32_t) * (P->n_tiles + 1), s)) != hipSuccess)
         return e;
     if (n == 0) return hipSuccess;
 
@@ -542,7 +580,7 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->n_groups = (int64_t)tail[0] + tail[1];
     hipLaunchKernelGGL(k_group_meta, dim3(blocks(nk, 256)), dim3(256), 0, s, order, flags,
                        gidx, (int64_t)nk, P->nchan, uvw, d_cc, g, cf, ant1, ant2, ant_dlm,
-                       du_dl, dv_dm, P->group_start, P->groups);
+                       du_dl, dv_dm, P->group_start, P->groups, P->geo);
     hipLaunchKernelGGL(k_group_end, dim3(1), dim3(64), 0, s, P->group_start, P->n_groups,
                        (int64_t)nk);
     hipLaunchKernelGGL(k_group_index, dim3(blocks(nk, 256)), dim3(256), 0, s, gidx, flags,
@@ -587,6 +625,8 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     hipLaunchKernelGGL(k_chunk_excl, dim3(blocks(nch, 256)), dim3(256), 0, s, tk_b,
                        P->chunk_start, nch, ntp, P->chunk_excl);
     hipLaunchKernelGGL(k_chunk_end, dim3(1), dim3(64), 0, s, P->chunk_start, nch, ntp);
+    hipLaunchKernelGGL(k_tile_ranges, dim3(blocks(P->n_tiles + 1, 256)), dim3(256), 0, s, tk_b,
+                       ntp, P->n_tiles, P->tile_tp);
     // with a kernel table the last-level cache holds, the gridder launches
     // chunks largest first (a stable sort: ties keep tile order), so the
     // long ones do not trail the launch; a larger table keeps tile order,
@@ -641,6 +681,13 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     if (P->period > 0)
         hipLaunchKernelGGL(k_single_gaps, dim3(blocks(nk, 256)), dim3(256), 0, s, order, gidx,
                            (int64_t)nk, P->period, single);
+    if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_group_kinds, dim3(blocks(ng, 256)), dim3(256), 0, s, P->group_start,
+                       ng, single, P->multi, (int32_t *)counter);
+    int32_t n_multi = 0;
+    (void)hipMemcpyAsync(&n_multi, counter, 4, hipMemcpyDeviceToHost, s);
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    P->n_multi = n_multi;
     hipLaunchKernelGGL(k_pair_group, dim3(blocks(n, 256)), dim3(256), 0, s, order, gidx,
                        (const int32_t *)single, (int64_t)nk, n, P->pair_group);
     return hipGetLastError();

@@ -555,7 +555,8 @@ namespace {
 // sized for the worst case and also holds the build's transient arrays).
 struct PackedLayout {
     size_t chan, order, gidx, pair_group, group_start, groups, tp_group, chunk_start,
-        chunk_tile, chunk_excl, chunk_order, tile_state, shared_tiles, total;
+        chunk_tile, chunk_excl, chunk_order, tile_state, shared_tiles, geo, tile_tp, multi,
+        total;
 };
 
 PackedLayout packed_layout(const lr_plan *P) {
@@ -575,6 +576,9 @@ PackedLayout packed_layout(const lr_plan *P) {
     L.chunk_order = take(P->chunk_order ? sizeof(int32_t) * P->n_chunks : 0);
     L.tile_state = take(sizeof(int32_t) * P->n_tiles);
     L.shared_tiles = take(sizeof(int32_t) * P->n_shared);
+    L.geo = take(sizeof(int64_t) * P->n_groups);
+    L.tile_tp = take(sizeof(int32_t) * (P->n_tiles + 1));
+    L.multi = take(sizeof(int32_t) * P->n_multi);
     L.total = off;
     return L;
 }
@@ -619,6 +623,9 @@ lr_status lr_plan_pack(const lr_plan *plan, void *buf, size_t bytes, lr_stream s
         move(Q->chunk_order, P->chunk_order, L.chunk_order, sizeof(int32_t) * P->n_chunks);
     move(Q->tile_state, P->tile_state, L.tile_state, sizeof(int32_t) * P->n_tiles);
     move(Q->shared_tiles, P->shared_tiles, L.shared_tiles, sizeof(int32_t) * P->n_shared);
+    move(Q->geo, P->geo, L.geo, sizeof(int64_t) * P->n_groups);
+    move(Q->tile_tp, P->tile_tp, L.tile_tp, sizeof(int32_t) * (P->n_tiles + 1));
+    move(Q->multi, P->multi, L.multi, sizeof(int32_t) * P->n_multi);
     Q->bytes_used = L.total;
     if (e != hipSuccess) { delete Q; return dev_fail(e, "plan pack"); }
     *out = Q;
@@ -837,6 +844,7 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
         if (e != hipSuccess) return dev_fail(e, "grid");
         return LR_OK;
     }
+    const CFView view = view_of(cf);
     hipError_t e = launch_grid_setup(
         P, A, (size_t)P->n_groups * vis->npol * cplx_bytes(precision), set ? sumwt : nullptr,
         sizeof(double) * cf->grid.nplane * vis->npol, set ? counters : nullptr, grid, precision,
@@ -845,7 +853,7 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
         e = launch_presum(P, va, precision, A, sumwt, counters, cf->grid.nplane, s);
     if (e == hipSuccess) {
         prof.begin();
-        e = launch_grid(P, view_of(cf), A, grid, precision, vis->npol, cf->grid.nx,
+        e = launch_grid(P, view, A, grid, precision, vis->npol, cf->grid.nx,
                         cf->grid.ny, mode, false, s);
         prof.end();
     }

@@ -19,6 +19,8 @@ constexpr int kTile = 32;          // gridder tile side (cells)
 constexpr int kChunkMax = 64;      // most (tile, group) pairs per gridder workgroup
 constexpr int kChunkCells = 32 * kTile * kTile;   // most footprint cells per workgroup
 constexpr int32_t kSingleRun = 1 << 30;   // pair_group flag: the group is one stretch of a track
+constexpr int32_t kSingleton = 1 << 29;   // pair_group flag: the group has one member
+constexpr int32_t kGroupFlags = kSingleRun | kSingleton;
 
 // ---------------------------------------------------------------------------
 // Per-channel constants formed on the host in FP64 (no contraction).
@@ -134,7 +136,8 @@ struct lr_plan {
     int32_t *order;            // [n_pairs] pair ids; kept (sorted) first; bit 30 set = skipped channel
     int32_t *gidx;             // [n_kept] group of each sorted kept pair
     int32_t *pair_group;       // [n_pairs] group of each pair in natural order (-1 dropped,
-                               // -2 skipped; kSingleRun set for single-run groups)
+                               // -2 skipped; kSingleRun set for single-run groups,
+                               // kSingleton for one-member groups)
     int64_t period;            // pairs between consecutive samples of one track (0: unknown)
     int32_t *group_start;      // [n_groups + 1]
     lr::GroupMeta *groups;     // [n_groups]
@@ -148,6 +151,10 @@ struct lr_plan {
     int64_t n_tiles;           // nplane * nty * ntx
     int32_t *shared_tiles;     // [n_shared] ids of the tiles in state 2
     int64_t n_shared;
+    int64_t *geo;              // [n_groups] (p_u, p_v, o_u, o_v) as int16, p_u lowest
+    int32_t *tile_tp;          // [n_tiles + 1] first (tile, group) pair of each tile
+    int32_t *multi;            // [n_multi] groups with more than one member
+    int64_t n_multi;
     const lr::ChanConst *cc;   // [nchan] channel constants (plane of each channel)
     size_t bytes_used;
 };

@@ -16,7 +16,7 @@ struct KeyLayout {
 
 struct PlanLayout {
     size_t chan, order, gidx, pair_group, group_start, groups, tp_group, chunk_start, chunk_tile,
-        chunk_excl, chunk_order, tile_state, shared_tiles, persistent;
+        chunk_excl, chunk_order, tile_state, shared_tiles, geo, tile_tp, multi, persistent;
     size_t keys_a, keys_b, vals_a, flags, scan, counter, temp;
     int64_t max_tp;
     size_t total;
