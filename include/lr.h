@@ -263,6 +263,22 @@ lr_status lr_grid_overwrite(const lr_cf *cf, const lr_vis *vis, lr_precision pre
                             void *grid, double *sumwt, int64_t *counters, void *work,
                             size_t work_bytes, lr_stream stream);
 
+/* Gridding G as lr_grid (accumulating; same arguments, layout, results and
+ * errors) for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * takes no workspace: the group sums (and the deterministic order's
+ * partial sums) live in a fixed 64 MiB device array of the library, one
+ * copy per GPU, held until the process ends; the call itself allocates
+ * nothing.  vis->plan must be a built plan (LR_E_ARG otherwise).  Plans
+ * whose scratch exceeds the array (more than 2,097,152 groups at 4 pols
+ * in FP32, 1,048,576 in FP64, fewer in the deterministic order) give
+ * LR_E_RANGE before anything is enqueued.  The array is shared by every
+ * call on the same GPU: calls that overlap on one GPU (different streams
+ * or threads) race and must be serialised by the caller.  The calling
+ * thread's current device must be the device of `stream`. */
+lr_status lr_grid_static(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
+                         void *grid, double *sumwt, int64_t *counters, lr_stream stream);
+
 /* Degridding D (Eq. ME-MOD-GRIDDED): vis = sum_t conj(Ct(o, t) phi(t)) grid[...]
  * for kept samples; flagged and dropped samples are written as 0.  No
  * weights enter the sum.  counters may be NULL. */

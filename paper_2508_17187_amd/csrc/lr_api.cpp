@@ -10,6 +10,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdlib>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -790,6 +791,37 @@ static size_t grid_scratch_bytes(const lr_vis *vis, lr_precision precision, bool
     return a_bytes + d_bytes;
 }
 
+// Fixed device scratch of lr_grid_static, one copy per GPU the library runs
+// on, held until the process ends.  Host code never passes `scratch` itself
+// (on the host it is only a stand-in for the symbol): the device address of
+// each GPU's copy comes from hipGetSymbolAddress with that GPU current, once
+// per device, and only that address reaches kernels.
+static constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_addr[kMaxDevices];
+}  // namespace
+
+// Device address of the current GPU's copy of `scratch`.
+static lr_status static_scratch(void **out) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return dev_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(LR_E_DEVICE, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return dev_fail(e, "scratch symbol address");
+        g_scratch_addr[dev] = p;
+    }
+    *out = g_scratch_addr[dev];
+    return LR_OK;
+}
+
 static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
                              void *grid, double *sumwt, int64_t *counters, void *work,
                              size_t work_bytes, lr_stream stream, int mode) {
@@ -873,6 +905,26 @@ lr_status lr_grid_overwrite(const lr_cf *cf, const lr_vis *vis, lr_precision pre
                             size_t work_bytes, lr_stream stream) {
     return grid_common(cf, vis, precision, grid, sumwt, counters, work, work_bytes, stream,
                        GRID_SET);
+}
+
+lr_status lr_grid_static(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
+                         void *grid, double *sumwt, int64_t *counters, lr_stream stream) {
+    if (!vis) return fail(LR_E_ARG, "vis descriptor is NULL");
+    if (!vis->plan)
+        return fail(LR_E_ARG, "lr_grid_static needs a binning plan (vis->plan): a transient "
+                              "plan would need workspace");
+    if (vis->npol < 1 || vis->npol > 4) return fail(LR_E_ARG, "npol must be 1, 2 or 4");
+    size_t a_bytes = 0;
+    const size_t need = grid_scratch_bytes(vis, precision, g_det.load() != 0, a_bytes);
+    if (need > kStaticScratchBytes)
+        return fail(LR_E_RANGE, "lr_grid_static: this plan needs %zu bytes of scratch, beyond "
+                                "the library's fixed %zu (%lld groups x %d pols); use lr_grid",
+                    need, kStaticScratchBytes, (long long)vis->plan->n_groups, vis->npol);
+    void *work = nullptr;
+    lr_status st = static_scratch(&work);
+    if (st != LR_OK) return st;
+    return grid_common(cf, vis, precision, grid, sumwt, counters, work, kStaticScratchBytes,
+                       stream, GRID_ADD);
 }
 
 lr_status lr_make_psf(const lr_cf *cf, const lr_vis *vis, lr_precision precision,

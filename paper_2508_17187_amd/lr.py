@@ -78,6 +78,8 @@ EXPORTS = {
                           C.c_void_p, C.c_size_t, C.c_void_p]),
     "lr_grid_overwrite": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
+    "lr_grid_static": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                 C.c_void_p, C.c_void_p]),
     "lr_degrid": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
                             C.c_void_p, C.c_size_t, C.c_void_p]),
     "lr_make_psf": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
@@ -391,6 +393,14 @@ def lr_grid_overwrite(cf, vis, precision, grid, sumwt=None, counters=None, work=
     _check(lib().lr_grid_overwrite(cf.handle, C.byref(d), precision, _ptr(grid), _ptr(sumwt),
                                    _ptr(counters), _ptr(work), work.numel(), _stream(stream)))
     return work
+
+
+def lr_grid_static(cf, vis, precision, grid, sumwt=None, counters=None, stream=None):
+    """lr_grid without workspace (the library's fixed scratch); vis.plan
+    must be set."""
+    d = vis.desc()
+    _check(lib().lr_grid_static(cf.handle, C.byref(d), precision, _ptr(grid), _ptr(sumwt),
+                                _ptr(counters), _stream(stream)))
 
 
 def lr_degrid(cf, vis, precision, grid, counters=None, work=None, stream=None):
