@@ -9,7 +9,9 @@ the imaging chi^2 whose gradient it is proportional to.
 
 import numpy as np
 
+from .cfbuild import airy_power
 from .conventions import C_LIGHT
+from .pswf import pswf_nystrom
 
 
 def centred_fft(img):
@@ -79,3 +81,44 @@ def dft_image(uvw_m, freq_hz, vis, weight, nx, ny, cell_l, cell_m, pol=0):
 def chi2(vis_obs, weight, vis_model):
     r = vis_obs - vis_model
     return float(np.sum(weight * (r.real ** 2 + r.imag ** 2)))
+
+
+def ps_taper(n, ps_support):
+    """The PS term's image-plane taper at n pixels: psi_0(c, 2 (i - n/2) / n),
+    c = pi S_ps / 2 (Table AWP-CFSETUP, PS; the screen's own sampling of it,
+    evaluated at the image pixels): the grid correction of tables whose
+    planes are not separable."""
+    psi = pswf_nystrom(np.pi * ps_support / 2.0)[0]
+    return psi(2.0 * (np.arange(n) - n // 2) / n)
+
+
+def pb_image(nx, ny, cell_l, cell_m, fg_hz, dish_m, fg_weight):
+    """Weight image of A-projection (the primary-beam normalisation of
+    Eq. ResIm's image when G carries the A term, Table AWP-CFSETUP): the
+    data hold the beam B_fg once and the kernel of G applies it again, so a
+    source at (l, m) images with sum_fg w_fg B_fg(rho)^2 / sum_fg w_fg,
+    B_fg(rho) = [2 J1(x)/x]^2 at x = pi D nu_fg rho / c, rho = sqrt(l^2 +
+    m^2), (l, m) = ((ix - nx/2) dl, (iy - ny/2) dm).  fg_weight: [..., n_fg]
+    sums of weights per frequency group; returns [..., ny, nx] (0 where the
+    weights sum to 0)."""
+    w = np.asarray(fg_weight, np.float64)
+    l = (np.arange(nx) - nx // 2) * cell_l
+    m = (np.arange(ny) - ny // 2) * cell_m
+    rho = np.sqrt(l[None, :] ** 2 + m[:, None] ** 2)
+    b2 = np.stack([airy_power(np.pi * dish_m * nu * rho / C_LIGHT) ** 2 for nu in fg_hz])
+    tot = w.sum(-1)
+    num = np.tensordot(w, b2, axes=([-1], [0]))
+    out = np.zeros(num.shape)
+    ok = tot > 0
+    out[ok] = num[ok] / tot[ok][..., None, None]
+    return out
+
+
+def normalise_aw(img, taper_x, taper_y, sumwt, pb, pb_min):
+    """Re(img) / (taper_x taper_y sumwt pb) where pb >= pb_min, 0 elsewhere;
+    img [..., ny, nx] with sumwt [...] and pb [..., ny, nx]."""
+    d = taper_y[:, None] * taper_x[None, :] * np.asarray(sumwt)[..., None, None] * pb
+    out = np.zeros(np.shape(pb))
+    ok = pb >= pb_min
+    out[ok] = np.real(img)[ok] / d[ok]
+    return out
