@@ -8,8 +8,7 @@ import time
 import numpy as np
 import pytest
 
-from paper_2508_17187_amd.serving import (Job, Scheduler, Server, cf_bytes, job_bytes,
-                                          latency_stats)
+from paper_2508_17187_amd.serving import Job, Scheduler, Server, latency_stats
 
 
 def simulate(jobs, budget, n_slots, duration, fail_ids=()):
@@ -44,9 +43,11 @@ def stream(n, rate=20.0, seed=0):
         ng = int(rng.choice([512, 1024, 2048, 4096]))
         nw = int(rng.integers(1, 65))
         key = (ng, nw)
+        # footprints of the right order: ~60 B per visibility plus the grid;
+        # a table of 441 offsets x S^2 taps per plane
+        cfb = 8 * 441 * 1883 * nw if nw > 1 else 8 * 101 * 101 * 49
         jobs.append(Job(i, "grid" if rng.random() < 0.5 else "degrid", key,
-                        job_bytes(nvis // 4, 1, 4, ng), cf_bytes(nw, 8, 32, 20) if nw > 1 else
-                        cf_bytes(1, 3, 3, 100), n_vis=nvis, t_arrival=float(t[i])))
+                        60 * nvis + 32 * ng * ng, cfb, n_vis=nvis, t_arrival=float(t[i])))
     return jobs
 
 
@@ -92,6 +93,45 @@ def test_resident_cf_is_shared_and_evicted_lru_when_budget_binds():
     s.submit(c, 2)
     adm = s.admit(2)
     assert adm and "A" not in s.cf and s.used == 800   # A evicted for B
+
+
+def test_model_grids_stay_resident_and_build_scratch_is_charged_once():
+    s = Scheduler(2000, 4)
+    # two degrid jobs on one model grid and one CF: one copy of each; the CF
+    # build's scratch is charged to the job that brings the table in only
+    a = Job(0, "degrid", "A", 100, 300, model_key="M", model_bytes=400, cf_build_bytes=50)
+    b = Job(1, "degrid", "A", 100, 300, model_key="M", model_bytes=400, cf_build_bytes=50)
+    s.submit(a, 0), s.submit(b, 0)
+    adm = s.admit(0)
+    assert [n for _, n in adm] == [True, False]
+    assert a.model_cold and not b.model_cold
+    assert a.charged == 150 and b.charged == 100
+    assert s.used == 300 + 400 + 150 + 100
+    s.complete(a, 1), s.complete(b, 1)
+    assert s.used == 700 and "M" in s.models and "A" in s.cf     # idle, still resident
+    # a job needing 1500 more bytes evicts idle resources, least recently
+    # used first, until it fits: the CF goes, the model grid stays
+    c = Job(2, "grid", "B", 1000, 500)
+    s.submit(c, 2)
+    assert s.admit(2) and s.used == 400 + 1500
+    assert s.take_evicted() == [("cf", "A")] and "M" in s.models
+
+
+def test_a_jobs_own_idle_resources_are_not_evicted_to_make_room_for_it():
+    s = Scheduler(1000, 4)
+    a = Job(0, "degrid", "A", 100, 300, model_key="M", model_bytes=300)
+    s.submit(a, 0)
+    s.admit(0)
+    s.complete(a, 1)                                  # A and M idle: 600 used
+    b = Job(1, "degrid", "A", 300, 300, model_key="M", model_bytes=300)
+    s.submit(b, 1)
+    assert s.admit(1)                                 # 600 + 300 fits without eviction
+    assert s.used == 900 and not s.take_evicted()
+    s.complete(b, 2)
+    c = Job(2, "degrid", "A", 500, 300, model_key="M", model_bytes=300)
+    s.submit(c, 2)
+    assert not s.admit(2)                             # would need its own A or M evicted
+    assert s.used == 600 and "A" in s.cf and "M" in s.models
 
 
 def test_oversized_job_is_rejected_alone_and_failures_are_isolated():
