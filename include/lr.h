@@ -319,6 +319,34 @@ lr_status lr_image_normalize(const lr_cf *cf, lr_precision precision, const void
                              const double *gcf_x, const double *gcf_y, const double *sumwt,
                              void *out, lr_stream stream);
 
+/* The grid correction of tables whose planes are not separable (an A term,
+ * or W planes beyond w = 0; Table AWP-CFSETUP): the PS term's taper that
+ * the kernels carry, at n image pixels, out[i] = psi_0(c, 2 (i - n/2) / n),
+ * c = pi S_ps / 2 (1 without a PS term).  out: device float64 [n]. */
+lr_status lr_ps_taper(const lr_cf *cf, int32_t n, void *out, lr_stream stream);
+
+/* Weight image of A-projection (the normalisation of Eq. ResIm's image when
+ * the kernels of G carry the A term; Table AWP-CFSETUP A-Projection rows):
+ * the data hold the beam once and G applies it again, so a source at (l, m)
+ * images with
+ *     out[P][pol][iy][ix] = sum_fg w[P][pol][fg] B_fg(rho)^2 / sum_fg w[P][pol][fg],
+ * B_fg = the table's A term (Airy power pattern of the dish at the group's
+ * frequency), rho = sqrt(l^2 + m^2), (l, m) = ((ix - nx/2) cell_l,
+ * (iy - ny/2) cell_m); 1 everywhere without an A term, 0 where the weights
+ * sum to 0.  fg_weight: device float64 [nplane][npol][n_fg], the sums of
+ * weights of each frequency group's channels (lr_sumwt on those channels);
+ * out: device float64 [nplane][npol][ny][nx]. */
+lr_status lr_pb_image(const lr_cf *cf, const double *fg_weight, void *out, lr_stream stream);
+
+/* lr_image_normalize with the weight image: out = Re(img) / (gcf_x[ix]
+ * gcf_y[iy] sumwt[P][pol] pb[P][pol][iy][ix]) where pb >= pb_min, 0 where
+ * it is below (outside the usable beam).  pb: device float64 of the image's
+ * shape (lr_pb_image); gcf_x, gcf_y typically from lr_ps_taper.  LR_E_ARG
+ * for pb_min <= 0. */
+lr_status lr_image_normalize_pb(const lr_cf *cf, lr_precision precision, const void *img,
+                                const double *gcf_x, const double *gcf_y, const double *sumwt,
+                                const double *pb, double pb_min, void *out, lr_stream stream);
+
 /* ---- mosaic rows of the imaging-mode table (Eq. CIJ) --------------------- */
 
 /* Change of phase centre of mosaic data, in place: every sample of a row

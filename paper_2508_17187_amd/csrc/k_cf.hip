@@ -20,8 +20,7 @@ namespace lr {
 
 constexpr int kLegTerms = 48;
 
-__global__ void k_pswf(double c, double *coef) {
-    if (threadIdx.x != 0) return;
+__device__ void pswf_coef(double c, double *coef) {
     double d[kLegTerms], e[kLegTerms], x[kLegTerms], y[kLegTerms], wk[kLegTerms];
     const double c2 = c * c;
     for (int k = 0; k < kLegTerms; ++k) {
@@ -80,6 +79,10 @@ __global__ void k_pswf(double c, double *coef) {
         p0 = -p0 * (n + 1.0) / (n + 2.0);
     }
     for (int k = 0; k < kLegTerms; ++k) coef[k] = x[k] / val0;
+}
+
+__global__ void k_pswf(double c, double *coef) {
+    if (threadIdx.x == 0) pswf_coef(c, coef);
 }
 
 __device__ double pswf_eval(const double *coef, double eta) {
@@ -311,6 +314,69 @@ size_t cf_work_bytes(int32_t M, int32_t O, int32_t h_max) {
 }
 
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// The PS term's taper at n image pixels, psi_0(c, 2 (i - n/2) / n) (the
+// screen's taper sampled at the pixels; 1 without a PS term).  One
+// workgroup: the first thread finds the Legendre coefficients.
+__global__ void k_ps_taper(double c, int use_ps, int32_t n, double *out) {
+    __shared__ double coef[kLegTerms];
+    if (use_ps && threadIdx.x == 0) pswf_coef(c, coef);
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+        out[i] = use_ps ? pswf_eval(coef, 2.0 * (double)(i - n / 2) / (double)n) : 1.0;
+}
+
+hipError_t launch_ps_taper(double c, int use_ps, int32_t n, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_ps_taper, dim3(1), dim3(256), 0, s, c, use_ps, n, out);
+    return hipGetLastError();
+}
+
+// Weight image of A-projection: every pixel of every (plane, pol) gets
+// sum_fg w[fg] B_fg(rho)^2 / sum_fg w[fg], B_fg the Airy power pattern of
+// the table's A term at the group's frequency (x = fscale[fg] rho).
+struct PBArgs {
+    double fscale[128];     // pi D nu_fg / c of every group
+    int32_t nx, ny, n_fg, use_a;
+    double cell_l, cell_m;
+    int64_t n_planes;
+};
+
+__global__ void k_pb_image(PBArgs a, const double *w, double *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)a.nx * a.ny;
+    if (i >= per * a.n_planes) return;
+    const int64_t pl = i / per;
+    const int64_t r = i - pl * per;
+    const int iy = (int)(r / a.nx), ix = (int)(r - (int64_t)iy * a.nx);
+    const double l = (double)(ix - a.nx / 2) * a.cell_l, m = (double)(iy - a.ny / 2) * a.cell_m;
+    const double rho = sqrt(l * l + m * m);
+    const double *wp = w + pl * a.n_fg;
+    double num = 0.0, den = 0.0;
+    for (int g = 0; g < a.n_fg; ++g) {
+        const double b = a.use_a ? airy_pow(a.fscale[g] * rho) : 1.0;
+        num += wp[g] * (b * b);
+        den += wp[g];
+    }
+    out[i] = den > 0.0 ? num / den : 0.0;
+}
+
+hipError_t launch_pb_image(const lr_cf *cf, const double *w, double *out, hipStream_t s) {
+    const lr_grid_spec &g = cf->grid;
+    PBArgs a;
+    a.n_fg = cf->spec.n_fg;
+    for (int k = 0; k < 128; ++k)
+        a.fscale[k] = k < a.n_fg ? M_PI * cf->spec.dish_m * cf->fg_hz[k] / kCLight : 0.0;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.use_a = (cf->spec.terms & LR_TERM_A) ? 1 : 0;
+    a.cell_l = g.cell_l;
+    a.cell_m = g.cell_m;
+    a.n_planes = (int64_t)g.nplane * g.npol;
+    const int64_t n = (int64_t)g.nx * g.ny * a.n_planes;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pb_image, dim3(nblk(n, 256)), dim3(256), 0, s, a, w, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_cf_build(const lr_cf *cf, const CFBuildArgs &a, void *work, hipStream_t s) {
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };

@@ -110,4 +110,38 @@ hipError_t launch_normalize(const void *img, const double *gx, const double *gy,
     return hipGetLastError();
 }
 
+// As k_normalize, also divided by the weight image pb (same layout as
+// out) where pb >= pb_min; 0 elsewhere.
+template <typename T>
+__global__ __launch_bounds__(256) void k_normalize_pb(const T *img, const double *gx,
+                                                      const double *gy, const double *sumwt,
+                                                      const double *pb, double pb_min,
+                                                      int32_t nx, int32_t ny, int64_t n_planes,
+                                                      T *out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t per = (int64_t)nx * ny;
+    if (i >= per * n_planes) return;
+    const int64_t pl = i / per;
+    const int64_t r = i - pl * per;
+    const int iy = (int)(r / nx), ix = (int)(r - (int64_t)iy * nx);
+    const double b = pb[i];
+    out[i] = b >= pb_min ? (T)((double)img[2 * i] / (gx[ix] * gy[iy] * sumwt[pl] * b)) : (T)0;
+}
+
+hipError_t launch_normalize_pb(const void *img, const double *gx, const double *gy,
+                               const double *sumwt, const double *pb, double pb_min,
+                               int32_t nx, int32_t ny, int64_t n_planes, int precision,
+                               void *out, hipStream_t s) {
+    const int64_t n = (int64_t)nx * ny * n_planes;
+    if (n == 0) return hipSuccess;
+    dim3 grd((unsigned)((n + 255) / 256)), blk(256);
+    if (precision == LR_F64)
+        hipLaunchKernelGGL(k_normalize_pb<double>, grd, blk, 0, s, (const double *)img, gx, gy,
+                           sumwt, pb, pb_min, nx, ny, n_planes, (double *)out);
+    else
+        hipLaunchKernelGGL(k_normalize_pb<float>, grd, blk, 0, s, (const float *)img, gx, gy,
+                           sumwt, pb, pb_min, nx, ny, n_planes, (float *)out);
+    return hipGetLastError();
+}
+
 }  // namespace lr

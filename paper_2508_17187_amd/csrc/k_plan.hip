@@ -394,6 +394,41 @@ __global__ void k_tile_ranges(const uint32_t *keys, int64_t n, int64_t n_tiles,
     tile_tp[t] = (int32_t)lo;
 }
 
+// Parts of the separable gridder: a tile's (tile, group) pairs in pieces of
+// at most kSepPart, so that no workgroup is left with a tile many times
+// heavier than the rest.  Keys sort the tiles by pair count, most first.
+__global__ void k_sep_count(const int32_t *tile_tp, int64_t n_tiles, uint32_t *key,
+                            int32_t *tile) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_tiles) return;
+    key[t] = ~(uint32_t)(tile_tp[t + 1] - tile_tp[t]);
+    tile[t] = (int32_t)t;
+}
+
+__global__ void k_sep_nparts(const int32_t *tile_tp, const int32_t *tile, int64_t n_tiles,
+                             int32_t *nparts) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tiles) return;
+    const int32_t t = tile[i];
+    const int32_t n = tile_tp[t + 1] - tile_tp[t];
+    nparts[i] = (n + kSepPart - 1) / kSepPart;
+}
+
+__global__ void k_sep_fill(const int32_t *tile_tp, const int32_t *tile, const int32_t *nparts,
+                           const int32_t *first, int64_t n_tiles, int4 *part, int32_t *shared,
+                           int32_t *n_shared) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_tiles) return;
+    const int32_t t = tile[i], np = nparts[i];
+    if (np == 0) return;
+    const int32_t b0 = tile_tp[t], b1 = tile_tp[t + 1];
+    // equal pieces, the last one shorter by the remainder
+    const int32_t len = (b1 - b0 + np - 1) / np;
+    for (int q = 0; q < np; ++q)
+        part[first[i] + q] = make_int4(t, b0 + q * len, min(b1, b0 + (q + 1) * len), np > 1);
+    if (np > 1) shared[atomicAdd(n_shared, 1)] = t;
+}
+
 // Group of every pair in natural (row, channel) order: >= 0 kept (bit
 // kSingleRun set for a single-run group, kSingleton for a one-member
 // group), -1 dropped, -2 skipped channel.
@@ -492,15 +527,20 @@ PlanLayout plan_layout(int64_t n_pairs, int32_t nchan, int32_t h_max, int64_t n_
     L.geo = take(sizeof(int64_t) * n);
     L.tile_tp = take(sizeof(int32_t) * (std::max<int64_t>(n_tiles, 1) + 1));
     L.multi = take(sizeof(int32_t) * n);
+    const int64_t nt = std::max<int64_t>(n_tiles, 1);
+    L.sep_part = take(sizeof(int4) * (nt + ntp / kSepPart + 1));
+    L.sep_shared = take(sizeof(int32_t) * nt);
     L.persistent = off;
-    // transient
-    L.keys_a = take(sizeof(uint64_t) * std::max(n, ntp));
-    L.keys_b = take(sizeof(uint64_t) * std::max(n, ntp));
-    L.vals_a = take(sizeof(int32_t) * std::max(n, ntp));
-    L.flags = take(sizeof(int32_t) * std::max(n, ntp));
-    L.scan = take(sizeof(int32_t) * std::max(n, ntp));
+    // transient (the tile sort of the separable gridder's parts needs
+    // n_tiles + 1 entries)
+    const int64_t nx_ = std::max(std::max(n, ntp), nt + 1);
+    L.keys_a = take(sizeof(uint64_t) * nx_);
+    L.keys_b = take(sizeof(uint64_t) * nx_);
+    L.vals_a = take(sizeof(int32_t) * nx_);
+    L.flags = take(sizeof(int32_t) * nx_);
+    L.scan = take(sizeof(int32_t) * nx_);
     L.counter = take(64);
-    L.temp = take(sort_temp_bytes(n, ntp));
+    L.temp = take(sort_temp_bytes(n, std::max(ntp, nt + 1)));
     L.max_tp = ntp;
     L.total = off;
     return L;
@@ -522,7 +562,8 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     int32_t *gidx = (int32_t *)(buf + L.gidx);
     unsigned long long *counter = (unsigned long long *)(buf + L.counter);
     void *temp = buf + L.temp;
-    size_t temp_bytes = sort_temp_bytes(n, L.max_tp);
+    size_t temp_bytes =
+        sort_temp_bytes(n, std::max<int64_t>(L.max_tp, tile_count(g.nx, g.ny, g.nplane) + 1));
     P->order = order;
     P->gidx = gidx;
     P->pair_group = (int32_t *)(buf + L.pair_group);
@@ -542,6 +583,10 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->tile_tp = (int32_t *)(buf + L.tile_tp);
     P->multi = (int32_t *)(buf + L.multi);
     P->n_multi = 0;
+    P->sep_part = (int4 *)(buf + L.sep_part);
+    P->n_sep_parts = 0;
+    P->sep_shared = (int32_t *)(buf + L.sep_shared);
+    P->n_sep_shared = 0;
     P->cc = d_cc;
     P->n_kept = P->n_groups = P->n_tile_pairs = P->n_chunks = P->taps = 0;
     if ((e = launch_zero(P->tile_state, sizeof(int32_t) * P->n_tiles, s)) != hipSuccess)
@@ -658,6 +703,35 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
     P->n_tile_pairs = ntp;
     P->n_chunks = nch;
     P->taps = (int64_t)taps;
+
+    // parts of the separable gridder, tiles with most pairs first
+    {
+        const int64_t nt = P->n_tiles;
+        uint32_t *ck_a = (uint32_t *)keys_a, *ck_b = (uint32_t *)keys_b;
+        int32_t *tid_s = (int32_t *)scan;
+        hipLaunchKernelGGL(k_sep_count, dim3(blocks(nt, 256)), dim3(256), 0, s, P->tile_tp, nt,
+                           ck_a, vals_a);
+        e = rocprim::radix_sort_pairs(temp, temp_bytes, ck_a, ck_b, vals_a, tid_s, (size_t)nt,
+                                      0, 32, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sep_nparts, dim3(blocks(nt, 256)), dim3(256), 0, s, P->tile_tp,
+                           tid_s, nt, flags);
+        int32_t *first = (int32_t *)ck_a;
+        e = rocprim::exclusive_scan(temp, temp_bytes, flags, first, (int32_t)0, (size_t)nt,
+                                    rocprim::plus<int32_t>(), s);
+        if (e != hipSuccess) return e;
+        if ((e = launch_zero(counter, 64, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_sep_fill, dim3(blocks(nt, 256)), dim3(256), 0, s, P->tile_tp,
+                           tid_s, flags, first, nt, P->sep_part, P->sep_shared,
+                           (int32_t *)counter);
+        int32_t tl[3] = {0, 0, 0};
+        (void)hipMemcpyAsync(&tl[0], first + nt - 1, 4, hipMemcpyDeviceToHost, s);
+        (void)hipMemcpyAsync(&tl[1], flags + nt - 1, 4, hipMemcpyDeviceToHost, s);
+        (void)hipMemcpyAsync(&tl[2], counter, 4, hipMemcpyDeviceToHost, s);
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        P->n_sep_parts = (int64_t)tl[0] + tl[1];
+        P->n_sep_shared = tl[2];
+    }
 
     // the row period of the data, then the natural-order group map
     int32_t rmax = (int32_t)std::min<int64_t>(P->nrow - 1, 1 << 16);

@@ -172,6 +172,8 @@ CFView view_of(const lr_cf *cf) {
     // kernel: its imaginary parts are rounding noise
     const uint32_t t = cf->spec.terms;
     v.real = !(t & LR_TERM_A) && (!(t & LR_TERM_W) || cf->spec.n_w == 1) ? 1 : 0;
+    v.h0 = cf->h[0];
+    v.off0 = cf->plane_off[0];
     return v;
 }
 
@@ -557,7 +559,7 @@ namespace {
 struct PackedLayout {
     size_t chan, order, gidx, pair_group, group_start, groups, tp_group, chunk_start,
         chunk_tile, chunk_excl, chunk_order, tile_state, shared_tiles, geo, tile_tp, multi,
-        total;
+        sep_part, sep_shared, total;
 };
 
 PackedLayout packed_layout(const lr_plan *P) {
@@ -580,6 +582,8 @@ PackedLayout packed_layout(const lr_plan *P) {
     L.geo = take(sizeof(int64_t) * P->n_groups);
     L.tile_tp = take(sizeof(int32_t) * (P->n_tiles + 1));
     L.multi = take(sizeof(int32_t) * P->n_multi);
+    L.sep_part = take(sizeof(int4) * P->n_sep_parts);
+    L.sep_shared = take(sizeof(int32_t) * P->n_sep_shared);
     L.total = off;
     return L;
 }
@@ -627,6 +631,8 @@ lr_status lr_plan_pack(const lr_plan *plan, void *buf, size_t bytes, lr_stream s
     move(Q->geo, P->geo, L.geo, sizeof(int64_t) * P->n_groups);
     move(Q->tile_tp, P->tile_tp, L.tile_tp, sizeof(int32_t) * (P->n_tiles + 1));
     move(Q->multi, P->multi, L.multi, sizeof(int32_t) * P->n_multi);
+    move(Q->sep_part, P->sep_part, L.sep_part, sizeof(int4) * P->n_sep_parts);
+    move(Q->sep_shared, P->sep_shared, L.sep_shared, sizeof(int32_t) * P->n_sep_shared);
     Q->bytes_used = L.total;
     if (e != hipSuccess) { delete Q; return dev_fail(e, "plan pack"); }
     *out = Q;
@@ -667,6 +673,38 @@ lr_status lr_image_normalize(const lr_cf *cf, lr_precision precision, const void
     hipError_t e = launch_normalize(img, gcf_x, gcf_y, sumwt, g.nx, g.ny,
                                     (int64_t)g.nplane * g.npol, precision, out,
                                     (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "image normalisation");
+    return LR_OK;
+}
+
+lr_status lr_ps_taper(const lr_cf *cf, int32_t n, void *out, lr_stream stream) {
+    if (!cf || !out) return fail(LR_E_ARG, "NULL argument");
+    if (n <= 0) return fail(LR_E_ARG, "n must be positive");
+    const int use_ps = (cf->spec.terms & LR_TERM_PS) ? 1 : 0;
+    hipError_t e = launch_ps_taper(M_PI * cf->spec.ps_support / 2.0, use_ps, n, (double *)out,
+                                   (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "PS taper");
+    return LR_OK;
+}
+
+lr_status lr_pb_image(const lr_cf *cf, const double *fg_weight, void *out, lr_stream stream) {
+    if (!cf || !fg_weight || !out) return fail(LR_E_ARG, "NULL argument");
+    hipError_t e = launch_pb_image(cf, fg_weight, (double *)out, (hipStream_t)stream);
+    if (e != hipSuccess) return dev_fail(e, "weight image");
+    return LR_OK;
+}
+
+lr_status lr_image_normalize_pb(const lr_cf *cf, lr_precision precision, const void *img,
+                                const double *gcf_x, const double *gcf_y, const double *sumwt,
+                                const double *pb, double pb_min, void *out, lr_stream stream) {
+    if (!cf || !img || !gcf_x || !gcf_y || !sumwt || !pb || !out)
+        return fail(LR_E_ARG, "NULL argument");
+    if (precision < LR_F64 || precision > LR_F32_CFBF16) return fail(LR_E_DTYPE, "bad precision");
+    if (!(pb_min > 0.0)) return fail(LR_E_ARG, "pb_min must be positive");
+    const lr_grid_spec &g = cf->grid;
+    hipError_t e = launch_normalize_pb(img, gcf_x, gcf_y, sumwt, pb, pb_min, g.nx, g.ny,
+                                       (int64_t)g.nplane * g.npol, precision, out,
+                                       (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(e, "image normalisation");
     return LR_OK;
 }
@@ -861,7 +899,7 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
         hipError_t e = launch_grid_setup(P, nullptr, 0, set ? sumwt : nullptr,
                                          sizeof(double) * cf->grid.nplane * vis->npol,
                                          set ? counters : nullptr, grid, precision, vis->npol,
-                                         cf->grid.nx, cf->grid.ny, set, s);
+                                         cf->grid.nx, cf->grid.ny, set, false, s);
         if (e == hipSuccess && sumwt)
             e = launch_sumwt_det(P, vis->weight, precision, vis->npol, cf->grid.nplane, part,
                                  sumwt, s);
@@ -876,11 +914,16 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
         if (e != hipSuccess) return dev_fail(e, "grid");
         return LR_OK;
     }
+    // the separable small-support gridder writes whole tiles itself: no
+    // shared tiles to clear first
+    // the separable small-support gridder writes whole tiles itself; only
+    // tiles it splits into several parts are cleared first (GRID_SET)
     const CFView view = view_of(cf);
+    const bool sep = sep_gridder(P, view, mode, false);
     hipError_t e = launch_grid_setup(
         P, A, (size_t)P->n_groups * vis->npol * cplx_bytes(precision), set ? sumwt : nullptr,
         sizeof(double) * cf->grid.nplane * vis->npol, set ? counters : nullptr, grid, precision,
-        vis->npol, cf->grid.nx, cf->grid.ny, set, s);
+        vis->npol, cf->grid.nx, cf->grid.ny, set, sep, s);
     if (e == hipSuccess)
         e = launch_presum(P, va, precision, A, sumwt, counters, cf->grid.nplane, s);
     if (e == hipSuccess) {

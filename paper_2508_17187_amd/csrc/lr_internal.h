@@ -21,6 +21,7 @@ constexpr int kChunkCells = 32 * kTile * kTile;   // most footprint cells per wo
 constexpr int32_t kSingleRun = 1 << 30;   // pair_group flag: the group is one stretch of a track
 constexpr int32_t kSingleton = 1 << 29;   // pair_group flag: the group has one member
 constexpr int32_t kGroupFlags = kSingleRun | kSingleton;
+constexpr int kSepPart = 4096;     // most (tile, group) pairs per workgroup of the separable gridder
 
 // ---------------------------------------------------------------------------
 // Per-channel constants formed on the host in FP64 (no contraction).
@@ -99,6 +100,8 @@ struct CFView {
     const int32_t *h;           // [n_w]
     int32_t O, n_w, n_fg, storage;
     int32_t real;               // every value real (no A term, no w-dependence)
+    int32_t h0;                 // half-width of w-plane 0
+    int64_t off0;               // element offset of plane (0, 0)
 };
 
 }  // namespace lr
@@ -155,6 +158,11 @@ struct lr_plan {
     int32_t *tile_tp;          // [n_tiles + 1] first (tile, group) pair of each tile
     int32_t *multi;            // [n_multi] groups with more than one member
     int64_t n_multi;
+    int4 *sep_part;            // [n_sep_parts] (tile, first pair, end pair, several parts)
+                               // of the separable gridder, tiles with most pairs first
+    int64_t n_sep_parts;
+    int32_t *sep_shared;       // [n_sep_shared] tiles split into several parts
+    int64_t n_sep_shared;
     const lr::ChanConst *cc;   // [nchan] channel constants (plane of each channel)
     size_t bytes_used;
 };

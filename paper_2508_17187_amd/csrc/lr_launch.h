@@ -16,7 +16,8 @@ struct KeyLayout {
 
 struct PlanLayout {
     size_t chan, order, gidx, pair_group, group_start, groups, tp_group, chunk_start, chunk_tile,
-        chunk_excl, chunk_order, tile_state, shared_tiles, geo, tile_tp, multi, persistent;
+        chunk_excl, chunk_order, tile_state, shared_tiles, geo, tile_tp, multi, sep_part,
+        sep_shared, persistent;
     size_t keys_a, keys_b, vals_a, flags, scan, counter, temp;
     int64_t max_tp;
     size_t total;
@@ -69,13 +70,19 @@ enum { GRID_ADD = 0, GRID_PSF = 1, GRID_SET = 2 };
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
                        int precision, int32_t npol, int32_t nx, int32_t ny, int32_t mode,
                        bool det, hipStream_t s);
+// Whether launch_grid takes the separable small-support gridder (one
+// workgroup per tile, every cell written once): then GRID_SET needs no
+// clearing of shared tiles beforehand.
+bool sep_gridder(const lr_plan *P, const CFView &cf, int32_t mode, bool det);
 // Set-up of a gridding call, one launch: zero the group sums A (a_bytes)
 // and, when given, sumwt and counters; under GRID_SET also the tiles that
 // several chunks share (they are then added to atomically).
+// sep: the separable gridder follows, whose shared tiles (split into
+// several parts) are the ones cleared under GRID_SET.
 hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *sumwt,
                              size_t sumwt_bytes, int64_t *counters, void *grid,
                              int precision, int32_t npol, int32_t nx, int32_t ny, bool set,
-                             hipStream_t s);
+                             bool sep, hipStream_t s);
 // h_max: widest half-width of the table (small supports take the
 // four-groups-per-wavefront degridder)
 hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
@@ -90,6 +97,14 @@ hipError_t launch_gcf(const CFView &cf, int64_t plane_base, int32_t h, float sc,
 hipError_t launch_normalize(const void *img, const double *gx, const double *gy,
                             const double *sumwt, int32_t nx, int32_t ny, int64_t n_planes,
                             int precision, void *out, hipStream_t s);
+
+hipError_t launch_normalize_pb(const void *img, const double *gx, const double *gy,
+                               const double *sumwt, const double *pb, double pb_min,
+                               int32_t nx, int32_t ny, int64_t n_planes, int precision,
+                               void *out, hipStream_t s);
+// PS taper at n image pixels (k_cf.hip); weight image of A-projection
+hipError_t launch_ps_taper(double c, int use_ps, int32_t n, double *out, hipStream_t s);
+hipError_t launch_pb_image(const lr_cf *cf, const double *w, double *out, hipStream_t s);
 
 // ---- minor cycle (k_hogbom.hip) -------------------------------------------------
 constexpr int kHogbomBlocks = 1024;      // workgroups of the peak search

@@ -104,6 +104,11 @@ EXPORTS = {
                             C.c_size_t, C.c_void_p]),
     "lr_image_normalize": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p, C.c_void_p,
                                      C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lr_ps_taper": (C.c_int, [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p]),
+    "lr_pb_image": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lr_image_normalize_pb": (C.c_int, [C.c_void_p, C.c_int, C.c_void_p, C.c_void_p,
+                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_double,
+                                        C.c_void_p, C.c_void_p]),
     "lr_status_str": (C.c_char_p, [C.c_int]),
     "lr_last_error": (C.c_char_p, []),
 }
@@ -369,6 +374,30 @@ def workspace_bytes(op, cf, vis, precision):
     return lib().lr_workspace_bytes(op, C.byref(cf.spec), C.byref(cf.grid), C.byref(d), precision)
 
 
+def workspace_bytes_for(op, grid, spec, nrow, nchan, npol, precision):
+    """lr_workspace_bytes from the specifications alone (no table built, no
+    data on the device); for the visibility operations it includes a
+    transient binning plan."""
+    fg = np.ascontiguousarray(spec["fg_hz"], np.float64)
+    cs = CFSpec(fg_hz=fg.ctypes.data, **{k: v for k, v in spec.items() if k != "fg_hz"})
+    d = VisDesc()
+    d.nrow, d.nchan, d.npol = int(nrow), int(nchan), int(npol)
+    n = lib().lr_workspace_bytes(op, C.byref(cs), C.byref(grid), C.byref(d), precision)
+    if n == 0:
+        raise LRError(LR_E_ARG, lib().lr_last_error().decode())
+    return n
+
+
+def cf_bytes_for(grid, spec):
+    """lr_cf_bytes from the specifications alone."""
+    fg = np.ascontiguousarray(spec["fg_hz"], np.float64)
+    cs = CFSpec(fg_hz=fg.ctypes.data, **{k: v for k, v in spec.items() if k != "fg_hz"})
+    n = lib().lr_cf_bytes(C.byref(cs), C.byref(grid))
+    if n == 0:
+        raise LRError(LR_E_ARG, lib().lr_last_error().decode())
+    return n
+
+
 def _work(op, cf, vis, precision, work, stream=None):
     n = workspace_bytes(op, cf, vis, precision)
     if n == 0:
@@ -462,6 +491,40 @@ def lr_image_normalize(cf, precision, img, gcf_x, gcf_y, sumwt, out=None, stream
                           else torch.float32, device=img.device)
     _check(lib().lr_image_normalize(cf.handle, precision, _ptr(img), _ptr(gcf_x), _ptr(gcf_y),
                                     _ptr(sumwt), _ptr(out), _stream(stream)))
+    return out
+
+
+def lr_ps_taper(cf, n, device="cuda", stream=None):
+    """The PS term's taper at n image pixels: float64 [n] on the device."""
+    out = torch.empty(n, dtype=torch.float64, device=device)
+    _check(lib().lr_ps_taper(cf.handle, n, _ptr(out), _stream(stream)))
+    return out
+
+
+def lr_pb_image(cf, fg_weight, stream=None):
+    """Weight image of A-projection, float64 [nplane, npol, ny, nx], from the
+    sums of weights per frequency group fg_weight (float64 device tensor
+    [nplane, npol, n_fg])."""
+    g = cf.grid
+    if fg_weight.dtype != torch.float64 or tuple(fg_weight.shape) != (g.nplane, g.npol,
+                                                                        cf.spec.n_fg):
+        raise LRError(LR_E_ARG, "fg_weight must be float64 [nplane, npol, n_fg]")
+    out = torch.empty((g.nplane, g.npol, g.ny, g.nx), dtype=torch.float64,
+                      device=fg_weight.device)
+    _check(lib().lr_pb_image(cf.handle, _ptr(fg_weight.contiguous()), _ptr(out),
+                             _stream(stream)))
+    return out
+
+
+def lr_image_normalize_pb(cf, precision, img, gcf_x, gcf_y, sumwt, pb, pb_min, out=None,
+                          stream=None):
+    """Re(img) / (gcf_x gcf_y sumwt pb) where pb >= pb_min, else 0."""
+    if out is None:
+        out = torch.empty(img.shape, dtype=torch.float64 if precision == LR_F64
+                          else torch.float32, device=img.device)
+    _check(lib().lr_image_normalize_pb(cf.handle, precision, _ptr(img), _ptr(gcf_x),
+                                       _ptr(gcf_y), _ptr(sumwt), _ptr(pb), pb_min, _ptr(out),
+                                       _stream(stream)))
     return out
 
 
