@@ -156,3 +156,58 @@ def test_config5_degrid_samples_and_adjoint(c5, two_chunks):
     e = rel(np.array(got), np.array(ref))
     say("sampled degrid rel-rms", e, "over", len(picks), "samples")
     assert len(picks) >= 4 and e <= 1e-5
+
+
+def test_config5_grid_sampled_cells(c5):
+    """The gridder at the large image's real shape (8192^2 x 4, A+W table
+    of 128 planes x 8 groups), one channel of the first chunk gridded by
+    lr_grid_overwrite: 40 random cells the channel's footprints reach
+    against the oracle gridding every row whose footprint covers one of
+    them (all the grid those cells receive)."""
+    wl, cf = c5
+    c = 37
+    cp = np.full(wl.obs.nchan, -1, np.int32)
+    cp[c] = 0
+    vis, wt = synth.chunk_values(R, wl.obs.nchan, wl.grid.npol, seed=5011)
+    v = lr.Vis(torch.as_tensor(np.ascontiguousarray(wl.obs.uvw[:R]), device=DEV),
+               wl.obs.freq_hz, cp, wl.chan_fg, vis=torch.as_tensor(vis, device=DEV),
+               weight=torch.as_tensor(wt, device=DEV), npol=wl.grid.npol)
+    v.plan = lr.Plan(cf, v)
+    g = W.empty_grid(wl, lr.LR_F32)
+    lr.lr_grid_overwrite(cf, v, lr.LR_F32, g)
+    got = g[0].cpu().numpy()
+    del g
+    torch.cuda.empty_cache()
+    # the oracle's map of the one channel
+    gs = wl.grid
+    one = lambda rows, ocf: Problem(np.ascontiguousarray(wl.obs.uvw[rows]),
+                                    wl.obs.freq_hz[c:c + 1], np.zeros(1, np.int32),
+                                    np.asarray(wl.chan_fg[c:c + 1], np.int32), gs.nx, gs.ny,
+                                    gs.npol, gs.nplane, gs.cell_l, gs.cell_m, ocf)
+    dummy = oracle.build_cf(gs, wl.cf, planes=set(), compact=True)
+    m = one(slice(0, R), dummy).map()[:, 0]
+    keep = m[:, 6] == 1
+    h = dummy.h
+    rng = np.random.default_rng(5012)
+    kr = np.nonzero(keep)[0]
+    cells = []
+    for i in rng.choice(kr, 40, replace=False):
+        hh = int(h[m[i, 4]])
+        cells.append((m[i, 1] + rng.integers(-hh, hh + 1), m[i, 0] + rng.integers(-hh, hh + 1)))
+    cells = np.array(cells)
+    hk = h[m[:, 4]]
+    cover = np.zeros(R, bool)
+    for cy, cx in cells:
+        cover |= keep & (np.abs(m[:, 0] - cx) <= hk) & (np.abs(m[:, 1] - cy) <= hk)
+    rows = np.nonzero(cover)[0]
+    fg = int(wl.chan_fg[c])
+    ks = set((fg, int(k)) for k in np.unique(m[rows, 4]))
+    say("config5 one-channel grid: cells", len(cells), "rows", rows.size, "planes", len(ks))
+    ocf = oracle.build_cf(gs, wl.cf, planes=ks, compact=True)
+    ref = one(rows, ocf).grid(vis[rows][:, c:c + 1].astype(np.complex128),
+                              wt[rows][:, c:c + 1].astype(np.float64))[0]
+    a = got[:, cells[:, 0], cells[:, 1]]
+    b = ref[:, cells[:, 0], cells[:, 1]]
+    e = rel(a, b)
+    say("config5 sampled-cell rel-rms", e)
+    assert e <= 1e-5

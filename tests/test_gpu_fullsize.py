@@ -1,7 +1,7 @@
-"""Parity at the benchmark's full size (W-projection: 13,478,400
-visibilities, 32 w-planes, 2048^2 x 4 grid) in the launch configuration
-bench.py times (binning plan, FP32 and FP16-CF forms), on outputs the
-oracle computes one by one:
+"""Parity at full size (W-projection: 13,478,400 visibilities, 32 w-planes,
+2048^2 x 4 grid) in the launch configuration bench.py times (binning plan,
+lr_grid_overwrite and lr_degrid; FP64, FP32 and FP16-CF forms), on outputs
+the oracle computes one by one:
 
 * degridding: 4000 random (row, channel) samples of the GPU result against
   the oracle degridding the same grid for just those rows;
@@ -26,7 +26,7 @@ if not torch.cuda.is_available():
 from paper_2508_17187_amd import lr  # noqa: E402
 from paper_2508_17187_amd import workload as W  # noqa: E402
 
-TOL = {"f32": 1e-5, "f16cf": 3e-3}
+TOL = {"f64": 1e-12, "f32": 1e-5, "f16cf": 3e-3}
 
 
 def say(*a):
@@ -46,14 +46,14 @@ def sub_problem(wl, rows, ocf):
                    wl.grid.ny, wl.grid.npol, wl.grid.nplane, wl.grid.cell_l, wl.grid.cell_m, ocf)
 
 
-@pytest.mark.parametrize("form", ["f32", "f16cf"])
+@pytest.mark.parametrize("form", ["f64", "f32", "f16cf"])
 def test_fullsize_degrid_sampled(c2, form):
     wl, m = c2
     p = lr.PRECISIONS[form]
     rng = np.random.default_rng(21)
     shape = (1, 4, wl.grid.ny, wl.grid.nx)
     x = (rng.standard_normal(shape, np.float32) + 1j * rng.standard_normal(shape, np.float32)
-         ).astype(np.complex64)
+         ).astype(np.complex128 if form == "f64" else np.complex64)
     cf = W.build_cf(wl, p)
     v = W.device_vis(wl, p)
     v.plan = lr.Plan(cf, v)
@@ -70,15 +70,20 @@ def test_fullsize_degrid_sampled(c2, form):
     assert e <= TOL[form]
 
 
-@pytest.mark.parametrize("form", ["f32", "f16cf"])
+@pytest.mark.parametrize("form", ["f64", "f32", "f16cf"])
 def test_fullsize_grid_sampled_cells(c2, form):
     wl, m = c2
     p = lr.PRECISIONS[form]
     cf = W.build_cf(wl, p)
     v = W.device_vis(wl, p)
     v.plan = lr.Plan(cf, v)
-    g = W.empty_grid(wl, p)
-    lr.lr_grid(cf, v, p, g)
+    # the gridding call bench.py times: a fresh grid written whole (garbage
+    # in the output buffer beforehand must not survive)
+    g = torch.full((1, 4, wl.grid.ny, wl.grid.nx), 7.0, dtype=torch.complex128 if form == "f64"
+                   else torch.complex64, device="cuda")
+    sw = torch.full((1, 4), 5.0, dtype=torch.float64, device="cuda")
+    cnt = torch.full((3,), 9, dtype=torch.int64, device="cuda")
+    lr.lr_grid_overwrite(cf, v, p, g, sumwt=sw, counters=cnt)
     got = g[0].cpu().numpy()                       # [pol][ny][nx]
     rng = np.random.default_rng(22)
     keep = m[..., 6] == 1
@@ -108,3 +113,10 @@ def test_fullsize_grid_sampled_cells(c2, form):
     e = np.linalg.norm(a - b) / np.linalg.norm(b)
     say("grid sampled-cell rel-rms", form, e)
     assert e <= TOL[form]
+    # cells no footprint reaches were written as 0, sums and counts replaced
+    far = got[:, :8, :8]
+    assert np.all(far == 0)
+    s_ref, c_ref = Problem.from_workload(wl, oracle.build_cf(wl.grid, wl.cf, planes=set(),
+                                                             compact=True)).sumwt(wl.weight)
+    assert np.array_equal(cnt.cpu().numpy(), c_ref)
+    np.testing.assert_allclose(sw.cpu().numpy(), s_ref, rtol=1e-12)
