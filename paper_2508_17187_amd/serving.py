@@ -262,6 +262,8 @@ class Server:
             s["resident_cfs"] = len(self.sched.cf)
             s["resident_models"] = len(self.sched.models)
             s["model_uploads"] = sum(1 for j in jobs if j.model_cold)
+            errs = collections.Counter(j.error[:160] for j in jobs if j.error is not None)
+            s["errors"] = dict(errs.most_common(5))
             waits = [j.t_admit - j.t_arrival for j in jobs if j.t_admit is not None]
             s["admission_wait_p50_s"] = float(np.percentile(waits, 50)) if waits else None
             s["admission_wait_p99_s"] = float(np.percentile(waits, 99)) if waits else None
@@ -279,14 +281,17 @@ class Server:
     def _request_loop(self):
         with self.lock:
             while not self.stop:
-                for job, new_cf in self.sched.admit(self.clock()):
+                admitted = self.sched.admit(self.clock())
+                # evictions first: a key evicted and brought back within the
+                # same batch keeps the event its new preparation registers
+                self._release(self.sched.take_evicted())
+                for job, new_cf in admitted:
                     job.cf_cold = new_cf
                     if new_cf:
                         self.ready[("cf", job.cf_key)] = threading.Event()
                     if job.model_cold:
                         self.ready[("model", job.model_key)] = threading.Event()
                     self.slot_q[job.slot].append((job, new_cf))
-                self._release(self.sched.take_evicted())
                 self.lock.notify_all()
                 self.lock.wait(timeout=0.05)
 

@@ -203,3 +203,24 @@ def test_threaded_server_with_fake_executor():
     assert ok == 47 and st["jobs_done"] == 47 and st["jobs_failed"] == 1
     assert exe.max_concurrency > 1                  # work overlapped
     assert st["peak_hbm_bytes"] <= st["hbm_budget"]
+
+
+def test_cf_evicted_and_brought_back_in_one_batch_is_prepared_again():
+    # X and Z resident and idle (X least recently used); A (new CF Y) evicts
+    # X, and B, admitted in the same batch, brings X back: B must build it
+    # and succeed, as must a later job that shares it
+    exe = FakeExecutor()
+    srv = Server(exe, hbm_budget=90, n_slots=3)
+    mk = lambda i, key: Job(i, "grid", key, 5, 30, n_vis=10)
+    srv.submit(mk(0, "X")).result(timeout=5)
+    srv.submit(mk(1, "Z")).result(timeout=5)
+    with srv.lock:                      # both queued before the loop looks
+        fa = srv.submit(mk(2, "Y"))
+        fb = srv.submit(mk(3, "X"))
+    assert fa.result(timeout=5).result == 4
+    assert fb.result(timeout=5).result == 6
+    assert srv.submit(mk(4, "X")).result(timeout=5).result == 8
+    st = srv.stats()
+    srv.close()
+    assert st["jobs_failed"] == 0 and st["errors"] == {}
+    assert exe.has_cf("X") and exe.has_cf("Y")
