@@ -1,17 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the gridding / degridding hot path on one MI355X.
 
-A step = grid every visibility into a fresh grid (lr_grid_overwrite: clear
-of the tiles no chunk owns, presum, gridder), then degrid every visibility
-from that grid (degridder + expand), over the W-projection
-workload: 351 baselines, 600 dumps, 16 channels, 4 correlations
-(13,478,400 visibilities), 32 w-planes with supports 17..65, O = 20, onto a
-2048 x 2048 x 4 grid.  Inputs are resident in HBM; the CF table
-(PreCompute) and the binning plan (PreSolvePrep) are built once before the
-timed region and reported separately.
+Headline workload: the large single image, every input resident in HBM:
+351 baselines x 14,400 dumps x 64 channels x 4 correlations
+(1,293,926,400 visibilities) in 13 chunks of 390,625 rows with one packed
+binning plan each, A+W kernels (128 w-planes, supports up to 129, O = 20)
+onto an 8192 x 8192 x 4 grid.  A step grids every chunk into a fresh grid
+(lr_grid_overwrite for the first chunk, lr_grid for the rest) and then
+degrids every chunk from that grid.  The CF table (PreCompute) and the
+plans (PreSolvePrep) are built once before the timed region and reported
+separately.  Further legs (W-projection in four precision forms, the
+Standard kernel, imaging, calibration, mosaic, deterministic order, the
+stream from host memory, serving) and the CPU oracle's rate follow.
 
 Prints one JSON line; `value` is visibilities gridded + degridded per second
-in the headline precision form.
+in the FP32 form.
 """
 
 import argparse
@@ -24,6 +27,7 @@ import time
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+METRIC = "visibilities gridded+degridded/sec, FP32/FP16-CF vs FP64; p50/p99 job latency"
 PEAK = {"f64": 78.6e12, "f32": 157.3e12, "f16cf": 157.3e12, "bf16cf": 157.3e12}
 HBM_PEAK = 8.0e12
 
@@ -81,6 +85,7 @@ def run_form(wl, form, steps, warmup, ev):
     wd = lr._work(lr.LR_OP_DEGRID, cf, vout, p, None)
     info = plan.info()
     sample_taps = per_sample_taps(cf, v)
+    kern = gridder_kernel(cf)
 
     def step(prof=None, marks=None):
         if marks:
@@ -155,6 +160,7 @@ def run_form(wl, form, steps, warmup, ev):
         "n_kept_pairs": info["n_kept"],
         "taps": info["taps"],
         "sample_taps": sample_taps,
+        "gridder_kernel": kern,
     }
     return res, g, vout.vis
 
@@ -180,8 +186,48 @@ def per_sample_taps(cf, v):
 
 
 ELEM = {"f64": 16, "f32": 8, "f16cf": 4, "bf16cf": 4}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_grid_tile_wproj2048_traffic.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2508_17187_amd", "csrc", "k_grid.hip")
+CSRC = os.path.join(ROOT, "paper_2508_17187_amd", "csrc")
+# source file of each timed kernel (with the shared device helpers)
+KERNEL_FILES = {"k_grid_tile": "k_grid.hip", "k_presum_col": "k_grid.hip",
+                "k_expand": "k_grid.hip", "k_grid_sep": "k_sep.hip",
+                "k_degrid": "k_degrid.hip", "k_degrid_small": "k_degrid.hip"}
+
+
+def kernel_source_sha(kernel):
+    """SHA-256 of the kernel's source file, the shared device helpers and
+    the binning plan (which decides the kernel's work decomposition and
+    launch order)."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("k_common.h", "k_plan.hip", KERNEL_FILES[kernel]):
+        h.update(open(os.path.join(CSRC, f), "rb").read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(workload, kernel, form):
+    """HBM bytes per launch of `kernel` on `workload` from the committed
+    counter summary profiles/<workload>_traffic.json (FETCH_SIZE and
+    WRITE_SIZE passes scaled by a plain device copy), or None when there is
+    none for this form or the kernel's source has changed since."""
+    try:
+        tr = json.load(open(os.path.join(ROOT, "profiles", workload + "_traffic.json")))
+        k = tr["kernels"][kernel]
+        if tr.get("form") == form and k.get("source_sha256") == kernel_source_sha(kernel):
+            return k["hbm_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        pass
+    return None
+
+
+def gridder_kernel(cf):
+    """The gridder an ordinary gridding call launches with this table:
+    k_grid_sep for a real table (no A term, one w-plane) with one frequency
+    group and a support of at most 15, k_grid_tile otherwise."""
+    sp = cf.spec
+    real = not (sp.terms & 4) and (not (sp.terms & 2) or sp.n_w == 1)
+    _, _, ne, po = cf.layout()
+    s2 = ((po[1] if len(po) > 1 else ne) - po[0]) // (sp.oversample + 1) ** 2
+    return "k_grid_sep" if real and sp.n_fg == 1 and s2 <= 15 * 15 else "k_grid_tile"
 
 
 def cf_read_bytes(form, r):
@@ -191,31 +237,23 @@ def cf_read_bytes(form, r):
     return min(r["taps"] * ELEM[form], r["cf_table_bytes"])
 
 
-def gridder_roofline(wl, form, r, with_traffic=True):
+def gridder_roofline(wl, form, r, traffic_workload=None):
     """Roofline of the gridder kernel (one launch grids all groups).
 
     Algorithmic flops: 8 per complex multiply-add, npol per kernel tap of
     every group.  Algorithmic bytes: the presummed group values (npol
     complex), every group's S x S sub-kernel once, the grid written once.
     The binding roof is the one with the longer time at peak."""
-    import hashlib
     npol = wl.grid.npol
+    kern = r.get("gridder_kernel", "k_grid_tile")
     cplx = 16 if form == "f64" else 8
     flops = 8.0 * npol * r["taps"]
     grid_bytes = wl.grid.nplane * npol * wl.grid.nx * wl.grid.ny * cplx
     bytes_ = r["n_groups"] * npol * cplx + cf_read_bytes(form, r) + grid_bytes
     t = r["grid_kernel_ms"] * 1e-3
     hbm = bytes_ / HBM_PEAK >= flops / PEAK[form]
-    traffic = None
-    try:
-        if not with_traffic:        # the counter summary covers the W-projection run
-            raise OSError
-        tr = json.load(open(TRAFFIC_FILE))
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if tr.get("kernel_source_sha256") == sha and tr.get("form") == form:
-            traffic = tr["hbm_bytes_per_launch"]
-    except (OSError, ValueError, KeyError):
-        pass
+    traffic = (None if traffic_workload is None
+               else traffic_per_launch(traffic_workload, kern, form))
     # the vector-ALU roof in complex multiply-adds (8 flops each) per second,
     # for the taps the method takes per sample and for those the merged
     # groups execute
@@ -225,12 +263,12 @@ def gridder_roofline(wl, form, r, with_traffic=True):
             "executed_cmac_per_s": npol * r["taps"] / t,
             "executed_frac": npol * r["taps"] / t / (PEAK[form] / 8.0)}
     if hbm:
-        return {"bound": "hbm", "kernel": "k_grid_tile (gridder)", "achieved": bytes_ / t / 1e9,
+        return {"bound": "hbm", "kernel": kern, "achieved": bytes_ / t / 1e9,
                 "peak": HBM_PEAK / 1e9, "unit": "GB/s", "frac": bytes_ / t / HBM_PEAK,
                 "traffic": traffic, "algorithmic_bytes_per_launch": bytes_,
                 "algorithmic_flops_per_launch": flops,
                 "alu_frac": flops / t / PEAK[form], "valu": valu, "kernel_ms": r["grid_kernel_ms"]}
-    return {"bound": "alu", "kernel": "k_grid_tile (gridder)", "achieved": flops / t / 1e12,
+    return {"bound": "alu", "kernel": kern, "achieved": flops / t / 1e12,
             "peak": PEAK[form] / 1e12, "unit": "TFLOP/s", "frac": flops / t / PEAK[form],
             "traffic": traffic, "algorithmic_bytes_per_launch": bytes_,
             "algorithmic_flops_per_launch": flops, "hbm_frac": bytes_ / t / HBM_PEAK,
@@ -481,13 +519,184 @@ def deterministic_bench(wl, form, steps):
             "repeat_bit_identical": same}
 
 
-def large_image_bench(steps, warmup, ev):
-    """The large single image: all 1,293,926,400 samples of the 8 h
-    observation streamed from pinned host memory in 13 chunks of 1e8
-    (copy of chunk i + 1 overlapped with planning and gridding of chunk i),
-    FP32, A+W kernels (128 planes, supports to 129, 8 frequency groups),
-    onto 8192^2 x 4.  Then one 1e8 chunk of the same layout through the
-    Standard kernel, where HBM bandwidth binds."""
+C5_WORKLOAD = ("large single image: 351 baselines (36 km) x 14,400 dumps (8 h at 2 s) x 64 "
+               "channels (2-4 GHz) x 4 pols = 1,293,926,400 visibilities in 13 chunks of "
+               "1e8; A+W kernels, 128 w-planes x 8 frequency groups, supports 17-129, O=20; "
+               "8192x8192x4 grid at 0.3 arcsec")
+
+
+def large_image_resident(form, steps, warmup, ev, rows=None):
+    """The large single image with every input resident in HBM: all
+    1,293,926,400 samples (sample values drawn on the device: they do not
+    change the work), 13 chunks of 390,625 rows with one packed plan each.
+    A step grids every chunk into one grid (lr_grid_overwrite for the
+    first chunk, lr_grid for the rest) and then degrids every chunk from
+    it.  The CF build (PreCompute) and the plans (PreSolvePrep) are built
+    once before the timed steps and reported separately."""
+    import numpy as np
+    import torch
+    import synth
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import workload as W
+    p = lr.PRECISIONS[form]
+    wl = synth.config5()
+    nrow = wl.obs.nrow if rows is None else rows
+    nchan, npol = wl.obs.nchan, wl.grid.npol
+    cdt, rdt = (torch.complex128, torch.float64) if p == lr.LR_F64 else (torch.complex64,
+                                                                         torch.float32)
+    torch.cuda.synchronize()
+    torch.cuda.reset_peak_memory_stats()
+    t0 = time.perf_counter()
+    cf = W.build_cf(wl, p)
+    torch.cuda.synchronize()
+    t_cf = time.perf_counter() - t0
+    R = synth.C5_CHUNK_ROWS
+    chunks = [(r, min(r + R, nrow)) for r in range(0, nrow, R)]
+    # one uvw array per chunk: a chunk of an odd number of rows would leave
+    # the next chunk's uvw rows off the 16-byte alignment the library needs
+    uvw = {r0: torch.as_tensor(np.ascontiguousarray(wl.obs.uvw[r0:r1]), device="cuda")
+           for r0, r1 in chunks}
+    vis = torch.empty((nrow, nchan, npol), dtype=cdt, device="cuda")
+    wt = torch.empty((nrow, nchan, npol), dtype=rdt, device="cuda")
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(5008)
+    for r0, r1 in chunks:
+        # FP32 draws (exact in FP64 too): every form grids the same values
+        sh = (r1 - r0, nchan, npol)
+        vis[r0:r1] = torch.complex(torch.randn(sh, generator=gen, device="cuda"),
+                                   torch.randn(sh, generator=gen, device="cuda"))
+        wt[r0:r1] = torch.rand(sh, generator=gen, device="cuda") + 0.5
+    vout = torch.empty_like(vis)
+    freq = wl.obs.freq_hz
+
+    def vdesc(r0, r1, data, plan=None):
+        return lr.Vis(uvw[r0], freq, wl.chan_plane, wl.chan_fg, vis=data[r0:r1],
+                      weight=wt[r0:r1], npol=npol, plan=plan)
+
+    # plans: built chunk by chunk in one worst-case build buffer, then packed
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plans, buf = [], None
+    for r0, r1 in chunks:
+        pl = lr.Plan(cf, vdesc(r0, r1, vis), buf=buf)
+        buf = pl.buf
+        plans.append(pl.packed())
+        del pl
+    torch.cuda.synchronize()
+    t_plan = time.perf_counter() - t0
+    build_bytes = int(buf.numel())
+    del buf
+    torch.cuda.empty_cache()
+    vs = [vdesc(r0, r1, vis, pl) for (r0, r1), pl in zip(chunks, plans)]
+    vo = [vdesc(r0, r1, vout, pl) for (r0, r1), pl in zip(chunks, plans)]
+    infos = [pl.info() for pl in plans]
+    sample_taps = sum(per_sample_taps(cf, v.with_(plan=None)) for v in vs)
+    g = W.empty_grid(wl, p)
+    sw = torch.zeros((wl.grid.nplane, npol), dtype=torch.float64, device="cuda")
+    # one workspace per operation, sized for the chunk that needs most
+    wg = torch.empty(max(lr.workspace_bytes(lr.LR_OP_GRID, cf, v, p) for v in vs),
+                     dtype=torch.uint8, device="cuda")
+    wd = torch.empty(max(lr.workspace_bytes(lr.LR_OP_DEGRID, cf, v, p) for v in vo),
+                     dtype=torch.uint8, device="cuda")
+
+    def step(prof=None):
+        for i, v in enumerate(vs):
+            if prof:
+                lr.lr_set_profile_events(*prof[0][i])
+            if i == 0:
+                lr.lr_grid_overwrite(cf, v, p, g, sumwt=sw, work=wg)
+            else:
+                lr.lr_grid(cf, v, p, g, sumwt=sw, work=wg)
+        for i, v in enumerate(vo):
+            if prof:
+                lr.lr_set_profile_events(*prof[1][i])
+            lr.lr_degrid(cf, v, p, g, work=wd)
+
+    for _ in range(warmup):
+        step()
+    n = len(vs)
+    prof = [([ev.pair() for _ in range(n)], [ev.pair() for _ in range(n)])
+            for _ in range(steps)]
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    a.record()
+    for i in range(steps):
+        step(prof[i])
+    b.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_step = a.elapsed_time(b) / steps * 1e-3
+    kg = [[ev.ms(*pr) for pr in st[0]] for st in prof]
+    kd = [[ev.ms(*pr) for pr in st[1]] for st in prof]
+    for st in prof:
+        for pr in st[0] + st[1]:
+            ev.free(*pr)
+    nvis = nrow * nchan * npol
+    grid_k = float(np.median([sum(x) for x in kg])) * 1e-3
+    degrid_k = float(np.median([sum(x) for x in kd])) * 1e-3
+    res = {
+        "form": form, "samples": nvis, "chunks": n, "steps": steps, "warmup": warmup,
+        "vis_per_s": nvis / t_step, "ms_per_step": 1e3 * t_step,
+        "wall_ms_per_step": 1e3 * wall / steps,
+        "grid_vis_per_s_kernels": nvis / grid_k, "degrid_vis_per_s_kernels": nvis / degrid_k,
+        "gridder_ms_per_step": 1e3 * grid_k, "degridder_ms_per_step": 1e3 * degrid_k,
+        "gridder_ms_per_chunk": [float(np.median([x[i] for x in kg])) for i in range(n)],
+        "degridder_ms_per_chunk": [float(np.median([x[i] for x in kd])) for i in range(n)],
+        "cf_build_s": t_cf, "cf_table_bytes": int(cf.nbytes),
+        "plan_build_s": t_plan, "plan_build_buffer_bytes": build_bytes,
+        "plan_packed_bytes": int(sum(pl.buf.numel() for pl in plans)),
+        "n_groups": int(sum(i["n_groups"] for i in infos)),
+        "n_kept_pairs": int(sum(i["n_kept"] for i in infos)),
+        "n_pairs": int(sum(i["n_pairs"] for i in infos)),
+        "taps": int(sum(i["taps"] for i in infos)),
+        "sample_taps": int(sample_taps),
+        "peak_hbm_bytes": int(torch.cuda.max_memory_allocated()),
+    }
+    # the grid of all chunks and the degridded values of the first chunk,
+    # for the error of one form against another
+    return res, g, vout[:chunks[0][1]].clone()
+
+
+def large_image_roofline(res):
+    """Vector-ALU roofline of the kernel that takes the larger share of a
+    large-image step (the gridder or the degridder).  Algorithmic flops per
+    launch: 8 per complex multiply-add for every kernel tap of every kept
+    sample (S_k^2 per (row, channel, pol), no merging), summed over the
+    chunk; the rate is the step's total over the kernel's total time (13
+    launches, one per chunk).  The peak is the published FP32 (FP64) vector
+    rate.  `traffic` is the measured HBM bytes per launch (mean over the 13
+    chunks) from the committed counter summary, when it matches the source."""
+    form = res["form"]
+    k = "gridder" if res["gridder_ms_per_step"] >= res["degridder_ms_per_step"] else "degridder"
+    kern = "k_grid_tile" if k == "gridder" else "k_degrid"
+    t = res[k + "_ms_per_step"] * 1e-3
+    n = res["chunks"]
+    flops = 8.0 * res["sample_taps"]
+    peak = PEAK[form]
+    traffic = traffic_per_launch("large_image", kern, form)
+    out = {"bound": "alu", "kernel": kern, "achieved": flops / t / 1e12, "peak": peak / 1e12,
+           "unit": "TFLOP/s", "frac": flops / t / peak, "traffic": traffic,
+           "algorithmic_flops_per_launch": flops / n, "launches_per_step": n,
+           "kernel_ms_per_launch": 1e3 * t / n,
+           # packed FP32 instructions are not used, so the FP32 vector rate
+           # reachable here is the non-packed one, equal to the FP64 peak
+           "frac_of_non_packed_rate": flops / t / PEAK["f64"],
+           "executed_frac": 8.0 * 4 * res["taps"] / t / peak,
+           # every group reads its S x S sub-kernel: bytes the kernel must
+           # fetch when no table plane stays in cache between groups
+           "kernel_tap_bytes_per_launch": res["taps"] * ELEM[form] / n}
+    if traffic is not None:
+        out["traffic_rate_gbps"] = traffic / (t / n) / 1e9
+        out["traffic_frac_of_hbm_peak"] = traffic / (t / n) / HBM_PEAK
+    return out
+
+
+def large_image_streamed(steps, warmup, ev):
+    """The large single image streamed from pinned host memory: every chunk
+    copied host to device (the copy of chunk i + 1 overlapped with chunk i),
+    planned and gridded, FP32: the PCIe-inclusive end-to-end rate."""
     import torch
     import synth
     from paper_2508_17187_amd import lr
@@ -495,18 +704,9 @@ def large_image_bench(steps, warmup, ev):
     from paper_2508_17187_amd.stream import ChunkStreamer
     p = lr.LR_F32
     wl = synth.config5()
-    out = {"workload": "8 h at 2 s, 351 baselines, 64 channels, 4 pols = 1,293,926,400 "
-                       "visibilities in 13 chunks; A+W CF 128 planes x 8 frequency groups, "
-                       "supports 17-129, O=20; 8192x8192x4 grid at 0.3 arcsec; FP32"}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    out = {"workload": C5_WORKLOAD + "; FP32; streamed from pinned host memory"}
     cf = W.build_cf(wl, p)
-    torch.cuda.synchronize()
-    out["cf_build_s"] = time.perf_counter() - t0
-    out["cf_gb"] = cf.nbytes / 1e9
     n, nchan, npol = wl.obs.nrow, wl.obs.nchan, wl.grid.npol
-    # sample values drawn on the device and staged in pinned host memory
-    # (their values do not change the work)
     uvw_p = torch.from_numpy(wl.obs.uvw).pin_memory()
     vis_p = torch.empty((n, nchan, npol), dtype=torch.complex64).pin_memory()
     wt_p = torch.empty((n, nchan, npol), dtype=torch.float32).pin_memory()
@@ -530,20 +730,26 @@ def large_image_bench(steps, warmup, ev):
     out.update({"samples": n * nchan * npol, "chunks": len(st.chunks()),
                 "grid_s": t, "grid_vis_per_s": n * nchan * npol / t,
                 "includes": "H2D of every chunk, a plan build per chunk, presum, gridder"})
-    del st, cf, g, vis_p, wt_p, uvw_p
-    torch.cuda.empty_cache()
-    # one chunk through the Standard kernel
+    return out
+
+
+def standard_kernel_chunk(steps, warmup, ev):
+    """One 1e8-visibility chunk of the large-image layout through the
+    Standard kernel (PS, S=7, O=100): the shape on which HBM bandwidth
+    binds."""
+    import synth
     wps = synth.config5_ps()
-    vals, wts = synth.chunk_values(R, nchan, npol, seed=5009)
+    R = synth.C5_CHUNK_ROWS
+    vals, wts = synth.chunk_values(R, wps.obs.nchan, wps.grid.npol, seed=5009)
     wps.obs.uvw = wps.obs.uvw[:R]
+    wps.obs.ant1, wps.obs.ant2 = wps.obs.ant1[:R], wps.obs.ant2[:R]
     wps.vis, wps.weight = vals, wts
     r, _, _ = run_form(wps, "f32", steps, warmup, ev)
-    roof = gridding_roofline(wps, "f32", r)
-    out["standard_kernel_chunk"] = {
-        "workload": "one 1e8-visibility chunk of the same layout, Standard kernel (PS, S=7, "
-                    "O=100), 8192x8192x4 grid, FP32", "result": r, "roofline": roof,
-        "roofline_gridder_kernel": gridder_roofline(wps, "f32", r, with_traffic=False)}
-    return out
+    return {"workload": "one 1e8-visibility chunk of the large-image layout, Standard kernel "
+                        "(PS, S=7, O=100), 8192x8192x4 grid, FP32", "result": r,
+            "roofline": gridding_roofline(wps, "f32", r),
+            "roofline_gridder_kernel": gridder_roofline(wps, "f32", r,
+                                                        traffic_workload="standard_chunk")}
 
 
 def image_bench(wl, form, steps, ev):
@@ -605,20 +811,20 @@ def image_bench(wl, form, steps, ev):
     return out
 
 
-def serving_bench(n_jobs=256, rate=20.0, budget_gb=64.0, slots=4, form="f32"):
-    """Poisson stream of grid / degrid jobs (configuration 4): visibility
-    counts log-uniform in [1e4, 2e7] (4 pols, one 3 GHz channel), grids of
-    512^2 .. 4096^2 x 4 at 0.2 arcsec, 1 .. 64 w-planes (w_max fixed from the
-    36 km layout at 4 GHz), 5-source skies.  Jobs are submitted at their
-    arrival times to a continuous-batching server; returns its stats."""
+def serving_jobs(n_jobs, rate, form):
+    """The serving stream (configuration 4): visibility counts log-uniform
+    in [1e4, 2e7] (4 pols, one 3 GHz channel), grids of 512^2 .. 4096^2 x 4
+    at 0.2 arcsec, 1 .. 64 w-planes (w_max fixed from the 36 km layout at
+    4 GHz), 5-source skies, grid or degrid with probability 1/2; one model
+    grid per grid size, shared by that size's degrid jobs.  Inputs are
+    staged in pinned host memory; footprints are the executor's exact
+    allocations."""
     import math
-    import threading
     import numpy as np
     import torch
     import synth
     from paper_2508_17187_amd import lr
     from paper_2508_17187_amd import serving as S
-    from paper_2508_17187_amd import workload as W
     p = lr.PRECISIONS[form]
     specs = synth.config4_jobs(n_jobs, rate)
     enu = synth.antenna_layout(27, 36000.0, seed=1004)
@@ -636,33 +842,57 @@ def serving_bench(n_jobs=256, rate=20.0, budget_gb=64.0, slots=4, form="f32"):
         freq = np.array([3.0e9])
         sky = synth.random_point_sky(5, seed=sp.seed, half_width_deg=0.05)
         vis = synth.dft_visibilities(uvw, freq, sky, 4, device="cuda").astype(np.complex64)
-        wt = np.ones(vis.shape, np.float32)
         N = sp.n_grid
         gs = lr.GridSpec(N, N, 4, 1, cell, cell)
         if sp.n_w == 1:
             cs = dict(terms=1, oversample=100, ps_support=7, n_w=1, w_max=0.0, h_min=3,
                       h_max=3, n_fg=1, fg_hz=np.array([3e9]), dish_m=25.0, screen_m=0,
                       storage=p)
-            cfb = S.cf_bytes(1, 3, 3, 100)
         else:
             cs = dict(terms=3, oversample=20, ps_support=7, n_w=sp.n_w, w_max=w_max, h_min=8,
                       h_max=32, n_fg=1, fg_hz=np.array([3e9]), dish_m=25.0, screen_m=0,
                       storage=p)
-            cfb = S.cf_bytes(sp.n_w, 8, 32, 20)
-        g = None
+        g, mkey = None, None
         if sp.op == "degrid":
+            mkey = N
             if N not in models:
-                models[N] = (rng.standard_normal((1, 4, N, N), np.float32)
-                             + 1j * rng.standard_normal((1, 4, N, N), np.float32)
-                             ).astype(np.complex64)
+                models[N] = torch.complex(torch.randn((1, 4, N, N)), torch.randn((1, 4, N, N))
+                                          ).pin_memory()
             g = models[N]
-        payload = dict(grid_spec=gs, cf_spec=cs, uvw=uvw, freq=freq,
-                       chan_plane=np.zeros(1, np.int32), vis=vis, weight=wt, grid=g)
-        jobs.append(S.Job(sp.job_id, sp.op, (N, sp.n_w), S.job_bytes(nrow, 1, 4, N) +
-                          600 * nrow, cfb, payload=payload, n_vis=vis.size,
-                          t_arrival=sp.arrival_s))
-    arrivals = [j.t_arrival for j in jobs]
+        payload = dict(grid_spec=gs, cf_spec=cs, uvw=torch.from_numpy(uvw).pin_memory(),
+                       freq=freq, chan_plane=np.zeros(1, np.int32),
+                       vis=torch.from_numpy(vis).pin_memory(),
+                       weight=torch.ones(vis.shape, dtype=torch.float32).pin_memory(), grid=g)
+        cfb, cfw = S.cf_footprint(gs, cs)
+        jobs.append(S.Job(sp.job_id, sp.op, (N, sp.n_w),
+                          S.job_footprint(sp.op, gs, cs, nrow, 1, 4, p,
+                                          resident_model=mkey is not None),
+                          cfb, payload=payload, n_vis=vis.size, t_arrival=sp.arrival_s,
+                          model_key=mkey,
+                          model_bytes=S.model_footprint(gs, p) if mkey is not None else 0,
+                          cf_build_bytes=cfw))
+    return jobs
+
+
+def serving_bench(n_jobs=256, rate=20.0, budget_gb=16.0, slots=4, form="f32", jobs=None):
+    """The serving stream submitted at its arrival times to a
+    continuous-batching server with an HBM budget that binds (16 GB: jobs
+    wait for memory as well as for slots); returns its stats.  rate=None
+    submits every job at once (arrivals far above capacity: throughput is
+    then the server's capacity)."""
+    import threading
+    import torch
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import serving as S
+    p = lr.PRECISIONS[form]
+    if jobs is None:
+        jobs = serving_jobs(n_jobs, rate or 20.0, form)
+    arrivals = [0.0 if rate is None else j.t_arrival for j in jobs]
     exe = S.GPUExecutor(slots, p)
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    base = torch.cuda.memory_allocated()
+    torch.cuda.reset_peak_memory_stats()
     srv = S.Server(exe, hbm_budget=int(budget_gb * (1 << 30)), n_slots=slots)
     t0 = time.perf_counter()
 
@@ -679,66 +909,144 @@ def serving_bench(n_jobs=256, rate=20.0, budget_gb=64.0, slots=4, form="f32"):
     srv.drain(timeout=900)
     st = srv.stats()
     srv.close()
-    st["n_jobs"] = n_jobs
-    st["arrival_rate_hz"] = rate
+    torch.cuda.synchronize()
+    st["allocator_peak_bytes"] = int(torch.cuda.max_memory_allocated() - base)
+    st["n_jobs"] = len(jobs)
+    st["arrival_rate_hz"] = rate if rate is not None else "all at once"
     st["slots"] = slots
     st["form"] = form
     st["total_vis"] = int(sum(j.n_vis for j in jobs))
+    del exe
+    torch.cuda.empty_cache()
     return st
 
 
-def cpu_baseline(wl, seconds=15.0):
-    """The CPU FP64 oracle, as it stands, on the first rows of the same
-    workload: grid + degrid, all host threads."""
+def cpu_baseline_large(sample_taps_per_vis, seconds=15.0, n_planes=12):
+    """The CPU FP64 oracle, as it stands, on a bounded sample of the large
+    image: the channels of the first frequency group, one at a time, each
+    with the rows whose samples fall on one of
+    the n_planes kernel planes most used among those whose support is near
+    the workload's root-mean-square support, all 4 pols (the oracle's table
+    holds only those planes).  Grid + degrid on all host threads, channels
+    added until about `seconds` of work; the rate in kernel taps per second
+    is turned into visibilities per second with the large image's mean taps
+    per visibility (its cost is linear in N_vis x C_sup)."""
     import numpy as np
     import oracle
+    import synth
     from oracle.native import Problem
-    ocf = oracle.build_cf(wl.grid, wl.cf)
+    wl = synth.config5()
     cores = os.cpu_count() or 1
     try:
         cores = len(os.sched_getaffinity(0))
     except Exception:
         pass
+    g = wl.grid
+    nchan, npol = wl.obs.nchan, g.npol
+    chans = [c for c in range(nchan) if wl.chan_fg[c] == 0]
+    dummy = oracle.build_cf(g, wl.cf, planes=set(), compact=True)
+    h = dummy.h
+    S = 2 * h.astype(np.int64) + 1
 
-    def run(rows):
-        pr = Problem(wl.obs.uvw[:rows], wl.obs.freq_hz, wl.chan_plane, wl.chan_fg, wl.grid.nx,
-                     wl.grid.ny, wl.grid.npol, wl.grid.nplane, wl.grid.cell_l, wl.grid.cell_m,
-                     ocf)
+    def problem(uvw, c, ocf):
+        # one channel of the observation (its frequency and A-term group)
+        return Problem(uvw, wl.obs.freq_hz[c:c + 1], np.zeros(1, np.int32),
+                       np.asarray(wl.chan_fg[c:c + 1], np.int32), g.nx, g.ny, npol, g.nplane,
+                       g.cell_l, g.cell_m, ocf)
+
+    def chan_map(c, nrows):
+        m = problem(wl.obs.uvw[:nrows], c, dummy).map()[:, 0]
+        return m[:, 6] == 1, m[:, 4].copy()
+
+    nprobe = wl.obs.nrow
+    c_mid = chans[len(chans) // 2]
+    keep, kk = chan_map(c_mid, nprobe)
+    s_rms = np.sqrt(sample_taps_per_vis)
+    near = (S >= 0.8 * s_rms) & (S <= 1.25 * s_rms)
+    counts = np.bincount(kk[keep], minlength=len(h))
+    counts[~near] = 0
+    top = np.argsort(-counts)[:n_planes]
+    top = top[counts[top] > 0]
+    planes = {(0, int(k)) for k in top}
+    t0 = time.perf_counter()
+    ocf = oracle.build_cf(g, wl.cf, planes=planes, compact=True)
+    t_cf = time.perf_counter() - t0
+    rng = np.random.default_rng(5010)
+    t, taps, nv, used = 0.0, 0, 0, []
+    for c in [c_mid] + [c for c in chans if c != c_mid]:
+        if t >= seconds:
+            break
+        if c != c_mid:
+            keep, kk = chan_map(c, nprobe)
+        sel = np.nonzero(keep & np.isin(kk, top))[0]
+        if len(sel) == 0:
+            continue
+        if t > 0:
+            # rows of this channel that fill the remaining time at the rate so far
+            sel = sel[:max(1, int((seconds - t) * nv / npol / t))]
+        pr = problem(np.ascontiguousarray(wl.obs.uvw[sel]), c, ocf)
+        shape = (len(sel), 1, npol)
+        wt = np.ones(shape)
+        vis = rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
         t0 = time.perf_counter()
-        g = pr.grid(wl.vis[:rows], wl.weight[:rows], nthreads=cores)
-        pr.degrid(g, wl.weight[:rows], nthreads=cores)
-        return time.perf_counter() - t0
+        gr = pr.grid(vis, wt, nthreads=cores)
+        pr.degrid(gr, wt, nthreads=cores)
+        t += time.perf_counter() - t0
+        del gr
+        taps += int(np.sum(S[kk[sel]] ** 2)) * npol
+        nv += len(sel) * npol
+        used.append(c)
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": taps / t / sample_taps_per_vis, "unit": "visibilities gridded+degridded/s",
+            "cores": cores, "kind": "oracle", "cpu_model": model,
+            "host_cpus": os.cpu_count(),
+            "sample": "large image, channels %s one at a time: the rows (of %d) whose "
+                      "samples lie on the %d kernel planes most used near the workload's rms "
+                      "support (w-planes %s, supports %s-%s), 4 pols = %d visibilities; grid + "
+                      "degrid in FP64 in %.1f s = %.3g taps/s, divided by the workload's %.1f "
+                      "taps per visibility (oracle table build %.1f s, not timed)"
+                      % (used, nprobe, len(planes), sorted(int(k) for k in top),
+                         int(S[top].min()), int(S[top].max()), nv, t, taps / t,
+                         sample_taps_per_vis, t_cf)}
 
-    rows = 351
-    t = run(rows)
-    while t < 1.0 and rows < wl.obs.nrow:
-        rows = min(wl.obs.nrow, rows * 4)
-        t = run(rows)
-    rows = int(min(wl.obs.nrow, max(rows, rows * seconds / max(t, 1e-3))))
-    t = run(rows)
-    n = rows * wl.obs.nchan * wl.grid.npol
-    return {"value": n / t, "unit": "visibilities gridded+degridded/s", "cores": cores,
-            "kind": "oracle",
-            "sample": "first %d of %d rows (all 16 channels, 4 pols): %d visibilities, "
-                      "grid + degrid in FP64, %.1f s" % (rows, wl.obs.nrow, n, t)}
+
+def rel_rms(a, b):
+    import torch
+    d = (a.to(torch.complex128) - b).flatten()
+    return float((d.abs().pow(2).sum() / b.flatten().abs().pow(2).sum()).sqrt().item())
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--form", default="f32", choices=["f64", "f32", "f16cf", "bf16cf"])
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--large-forms", default="f16cf,f64",
+                    help="forms of the large image measured beside FP32 (min(steps, 3) "
+                         "steps each)")
     ap.add_argument("--forms", default="f32,f16cf,bf16cf,f64",
-                    help="forms measured beside the headline one")
+                    help="forms of the W-projection workload")
+    ap.add_argument("--large-rows", type=int, default=0,
+                    help="rows of the large image (0 = all 5,054,400)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--serving-jobs", type=int, default=256,
                     help="jobs in the serving stream (0 = skip it)")
-    ap.add_argument("--no-large", dest="large", action="store_false",
-                    help="skip the large single image (1.3e9 visibilities streamed)")
-    ap.add_argument("--no-ps", dest="ps", action="store_false",
-                    help="skip the Standard-kernel (HBM-bound) workload")
+    ap.add_argument("--legs", default="all",
+                    help="comma list of legs after the headline (wproj, image, cf_cache, "
+                         "calibration, mosaic, deterministic, standard, standard_chunk, "
+                         "streamed, serving), 'all' or ''")
+    ap.add_argument("--no-legs", dest="legs", action="store_const", const="",
+                    help="only the large image (headline) and the CPU baseline")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the headline (profiling runs of single legs)")
     ap.add_argument("--copy-calib", action="store_true",
                     help="run one 1 GiB device copy first (scale of the HBM byte counters)")
     args = ap.parse_args()
@@ -757,50 +1065,130 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    log("generating the W-projection workload")
-    t0 = time.perf_counter()
-    wl = synth.config2_wproj(dft_device="cuda")
-    log("  %d visibilities in %.1f s" % (wl.nsamples, time.perf_counter() - t0))
     ev = HipEvents()
-    forms = [args.form] + [f for f in args.forms.split(",") if f and f != args.form]
-    res, grids = {}, {}
-    for f in forms:
-        log("form", f)
-        r, g, dv = run_form(wl, f, args.steps, args.warmup, ev)
-        res[f] = r
-        grids[f] = (g, dv)
+    rows = args.large_rows or None
+    legs = set(x for x in args.legs.split(",") if x)
+
+    def want(name):
+        return "all" in legs or name in legs
+
+    out = {}
+    if not args.no_large:
+        out = headline(args, ev, rows)
+    run_legs(args, ev, want, out)
+    if not args.no_cpu_baseline and "large_image_forms" in out:
+        log("cpu baseline")
+        out["cpu_baseline"] = cpu_baseline_large(
+            out["large_image_forms"]["f32"]["sample_taps"]
+            / out["large_image_forms"]["f32"]["samples"], args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def headline(args, ev, rows):
+    """The large single image, inputs resident in HBM: FP32 (the value)
+    and the other forms asked for."""
+    import torch
+    log("large image, FP32, %d steps after %d warm-up" % (args.steps, args.warmup))
+    head, g32, v32 = large_image_resident("f32", args.steps, args.warmup, ev, rows=rows)
+    log("  ", json.dumps(head))
+    large = {"f32": head}
+    g32h = g32
+    for f in [f for f in args.large_forms.split(",") if f and f != "f32"]:
+        torch.cuda.empty_cache()
+        log("large image,", f)
+        r, gf, vf = large_image_resident(f, min(args.steps, 3), 1, ev, rows=rows)
+        large[f] = r
+        if f == "f64":
+            large["f32"]["grid_rel_rms_vs_f64"] = rel_rms(g32h, gf)
+            large["f32"]["degrid_rel_rms_vs_f64_first_chunk"] = rel_rms(v32, vf)
+            if "_f16" in large:
+                gh, vh = large.pop("_f16")
+                large["f16cf"]["grid_rel_rms_vs_f64"] = rel_rms(gh, gf)
+                large["f16cf"]["degrid_rel_rms_vs_f64_first_chunk"] = rel_rms(vh, vf)
+        elif f in ("f16cf", "bf16cf"):
+            large["_f16"] = (gf, vf)
+        del gf, vf
         log("  ", json.dumps(r))
-    if "f64" in grids:
-        g64, v64 = grids["f64"]
-        for f in forms:
-            g, dv = grids[f]
-            res[f]["grid_rel_rms_vs_f64"] = float(
-                ((g.to(torch.complex128) - g64).norm() / g64.norm()).item())
-            res[f]["degrid_rel_rms_vs_f64"] = float(
-                ((dv.to(torch.complex128) - v64).norm() / v64.norm()).item())
-        for f in forms:
-            res[f]["speedup_vs_f64"] = res[f]["vis_per_s"] / res["f64"]["vis_per_s"]
-    del grids
-    log("residual image")
-    images = image_bench(wl, args.form, args.steps, ev)
-    log("  ", json.dumps(images))
-    log("CF cache")
-    cache = cf_cache_bench(wl, args.form)
-    log("  ", json.dumps(cache))
-    log("calibration")
-    calib = calibration_bench(wl, args.form, args.steps)
-    log("  ", json.dumps(calib))
-    log("mosaic")
-    mosaic = mosaic_bench(wl, args.form, args.steps)
-    log("  ", json.dumps(mosaic))
-    log("deterministic order")
-    determ = deterministic_bench(wl, args.form, args.steps)
-    log("  ", json.dumps(determ))
-    hbm = None
-    if args.ps:
-        # the same data through the Standard kernel (PS, S = 7, O = 100, one
-        # plane): the shape on which HBM bandwidth binds
-        log("standard-kernel (PS) workload")
+    large.pop("_f16", None)
+    if "f64" in large:
+        for f in list(large):
+            large[f]["speedup_vs_f64"] = large[f]["vis_per_s"] / large["f64"]["vis_per_s"]
+    del g32, g32h, v32
+    torch.cuda.empty_cache()
+    roof = large_image_roofline(head)
+    out = {
+        "metric": METRIC,
+        "value": head["vis_per_s"],
+        "unit": "visibilities/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded antenna layout and tracks; sample values drawn on the "
+                "device, which do not change the work)",
+        "config": {"workload": C5_WORKLOAD + ("" if rows is None else "; first %d rows" % rows),
+                   "form": "f32"},
+        "roofline": roof,
+        "large_image_forms": large,
+    }
+    return out
+
+
+def run_legs(args, ev, want, out):
+    import torch
+    import synth
+    if any(want(x) for x in ("wproj", "image", "cf_cache", "calibration", "mosaic",
+                             "deterministic")):
+        log("generating the W-projection workload")
+        wl = synth.config2_wproj(dft_device="cuda")
+        if want("wproj"):
+            res, grids = {}, {}
+            forms = [f for f in args.forms.split(",") if f]
+            for f in forms:
+                log("W-projection form", f)
+                r, g, dv = run_form(wl, f, args.steps, args.warmup, ev)
+                res[f] = r
+                grids[f] = (g, dv)
+                log("  ", json.dumps(r))
+            if "f64" in grids:
+                g64, v64 = grids["f64"]
+                for f in forms:
+                    g, dv = grids[f]
+                    res[f]["grid_rel_rms_vs_f64"] = rel_rms(g, g64)
+                    res[f]["degrid_rel_rms_vs_f64"] = rel_rms(dv, v64)
+                for f in forms:
+                    res[f]["speedup_vs_f64"] = res[f]["vis_per_s"] / res["f64"]["vis_per_s"]
+            del grids
+            wproj = {"workload": "W-projection: 351 baselines x 600 dumps x 16 channels x 4 "
+                                 "pols = 13,478,400 visibilities; 32 w-planes, supports 17-65, "
+                                 "O=20; 2048x2048x4 grid at 0.2 arcsec", "forms": res}
+            if "f32" in res:
+                wproj["roofline"] = gridder_roofline(wl, "f32", res["f32"],
+                                                     traffic_workload="wproj2048")
+            out["wproj"] = wproj
+        if want("image"):
+            log("residual image")
+            out["image"] = image_bench(wl, "f32", args.steps, ev)
+        if want("cf_cache"):
+            log("CF cache")
+            out["cf_cache"] = cf_cache_bench(wl, "f32")
+        if want("calibration"):
+            log("calibration")
+            out["calibration"] = calibration_bench(wl, "f32", args.steps)
+        if want("mosaic"):
+            log("mosaic")
+            out["mosaic"] = mosaic_bench(wl, "f32", args.steps)
+        if want("deterministic"):
+            log("deterministic order")
+            out["deterministic"] = deterministic_bench(wl, "f32", args.steps)
+        del wl
+        torch.cuda.empty_cache()
+    if want("standard"):
+        log("standard-kernel (PS) workloads")
         wps = synth.config2_ps(dft_device="cuda")
         hbm = {"workload": "W-projection data with the Standard kernel: PS only, S=7, "
                            "O=100, 2048x2048x4 grid", "forms": {}}
@@ -812,58 +1200,32 @@ def main():
                                      / hbm["forms"]["f64"]["vis_per_s"])
         hbm["roofline"] = gridding_roofline(wps, "f32", hbm["forms"]["f32"])
         hbm["roofline_gridder_kernel"] = gridder_roofline(wps, "f32", hbm["forms"]["f32"],
-                                                          with_traffic=False)
-        del wps
-    head = res[args.form]
-    roof = gridder_roofline(wl, args.form, head)
-    out = {
-        "metric": "visibilities gridded+degridded/sec",
-        "value": head["vis_per_s"],
-        "unit": "visibilities/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": head["ms_per_step"],
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"f64": "f64", "f32": "f32", "f16cf": "f32 (fp16 CF)",
-                  "bf16cf": "f32 (bf16 CF)"}[args.form],
-        "data": "synthetic (seeded 200-source sky, direct-sum visibilities, Gaussian noise)",
-        "config": {"workload": "W-projection: 351 baselines x 600 dumps x 16 channels x 4 "
-                               "pols = 13,478,400 visibilities; 32 w-planes, supports 17-65, "
-                               "O=20; 2048x2048x4 grid at 0.2 arcsec",
-                   "form": args.form},
-        "roofline": roof,
-        "forms": res,
-    }
-    out["image"] = images
-    out["cf_cache"] = cache
-    out["calibration"] = calib
-    out["mosaic"] = mosaic
-    out["deterministic"] = determ
-    if hbm is not None:
+                                                          traffic_workload="standard2048")
         out["hbm_bound_workload"] = hbm
-    if args.large:
-        log("large single image")
-        del wl
+        del wps
         torch.cuda.empty_cache()
-        out["large_image"] = large_image_bench(args.steps, args.warmup, ev)
-        log("  ", json.dumps(out["large_image"]))
-        wl = None
-    if args.serving_jobs > 0:
+    if want("standard_chunk"):
+        log("standard-kernel chunk of the large image")
+        out["standard_kernel_chunk"] = standard_kernel_chunk(args.steps, args.warmup, ev)
+        log("  ", json.dumps(out["standard_kernel_chunk"]))
+        torch.cuda.empty_cache()
+    if want("streamed"):
+        log("large image streamed from host memory")
+        out["large_image_streamed"] = large_image_streamed(args.steps, args.warmup, ev)
+        log("  ", json.dumps(out["large_image_streamed"]))
+        torch.cuda.empty_cache()
+    if want("serving") and args.serving_jobs > 0:
         log("serving stream of %d jobs" % args.serving_jobs)
-        wl = None
-        torch.cuda.empty_cache()
-        out["serving"] = serving_bench(args.serving_jobs, form=args.form)
-        log("  ", json.dumps(out["serving"]))
-        wl = None
-    if not args.no_cpu_baseline:
-        log("cpu baseline")
-        if wl is None:
-            wl = synth.config2_wproj(dft_device="cuda")
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+        jobs = serving_jobs(args.serving_jobs, 20.0, "f32")
+        serving = {"stream_20_per_s": serving_bench(rate=20.0, jobs=jobs)}
+        log("  ", json.dumps(serving["stream_20_per_s"]))
+        for j in jobs:
+            j.t_admit = j.t_done = j.error = j.result = None
+            j.cf_cold = j.model_cold = False
+            j.charged = 0
+        serving["all_at_once"] = serving_bench(rate=None, jobs=jobs)
+        log("  ", json.dumps(serving["all_at_once"]))
+        out["serving"] = serving
 
 
 if __name__ == "__main__":

@@ -17,7 +17,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblr.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["lr_api.cpp", "k_plan.hip", "k_cf.hip", "k_grid.hip", "k_image.hip", "k_hogbom.hip",
+SOURCES = ["lr_api.cpp", "k_plan.hip", "k_cf.hip", "k_grid.hip", "k_sep.hip", "k_degrid.hip", "k_image.hip", "k_hogbom.hip",
            "k_cal.hip", "k_mosaic.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1,0 +1,228 @@
+// Degridding D (Eq. ME-MOD-GRIDDED): one wavefront (or a quarter of one for
+// supports up to 15) per group gathers sum_t conj(Ct phi) grid over the
+// footprint and reduces across lanes.
+#include "k_common.h"
+
+namespace lr {
+
+// ---------------------------------------------------------------------------
+struct DegridArgs {
+    const GroupMeta *groups;
+    int64_t n_groups;
+    const void *grid;
+    void *Vg;
+    CFView cf;
+    int32_t nx, ny;
+    int64_t pol_stride;
+};
+
+// Taps per lane whose loads are in flight together in the degridder: 4, or
+// 8 with 4-byte (FP16 / BF16) kernel values, whose raw words take half the
+// registers.
+constexpr int kDegridTaps = 4;
+
+// One wavefront per group: lanes walk the footprint taps in row-major order,
+// four or eight taps per lane in flight; the sub-kernel and the footprint's
+// corner cell (per pol) are scalar base addresses and a lane carries 32-bit
+// offsets, advanced by 64 taps at a time without division.
+template <typename T, int ST, int NPOL, bool PO, bool RE>
+__global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
+    constexpr int E = CFRaw<ST>::bytes;
+    constexpr int NT = E <= 4 ? 2 * kDegridTaps : kDegridTaps;
+    typedef typename std::conditional<RE, typename CFReal<ST>::R, typename CFRaw<ST>::R>::type Raw;
+    const int lane = threadIdx.x & 63;
+    // consecutive groups (same plane, neighbouring footprints) run side by
+    // side across the XCDs, which share the last-level cache
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + uni(threadIdx.x >> 6);
+    if (g >= a.n_groups) return;
+    const GroupMeta gm = a.groups[g];
+    const int h = uni(gm.h);
+    const int S = 2 * h + 1;
+    const int SS = S * S;
+    const float sc = gm.sc;
+    const bool cj = uni(gm.conj) != 0;
+    const char *cfb = (const char *)a.cf.table + uni64(gm.cf_off) * E;
+    // corner cell (tap (0, 0)) of pol 0
+    const int64_t corner = uni64(gm.cell) - (int64_t)h * a.nx - h;
+    const int64_t pstride = a.pol_stride * (int64_t)(2 * sizeof(T));
+    // one scalar base per pol (its byte offset made opaque, so that a lane's
+    // offset is added to it rather than folded into 64-bit vector arithmetic)
+    const char *gbp[NPOL];
+    for (int p = 0; p < NPOL; ++p)
+        gbp[p] = (const char *)a.grid + uni64(corner * (int64_t)(2 * sizeof(T)) + p * pstride);
+    const int row = a.nx * (int)(2 * sizeof(T));          // bytes per grid row
+    // lane's first tap and the per-step advance of 64 taps
+    const int dty = 64 / S, dtx = 64 - dty * S;
+    int ty = lane / S, tx = lane - (lane / S) * S;
+    int goff = ty * row + tx * (int)(2 * sizeof(T));
+    cpx<T> sum[NPOL];
+    for (int p = 0; p < NPOL; ++p) sum[p] = {(T)0, (T)0};
+    for (int t0 = 0; t0 < SS; t0 += 64 * NT) {
+        Raw cr[NT];
+        cpx<T> gv[NT][NPOL];
+        bool ok[NT];
+        int txs[NT], tys[NT];
+        for (int u = 0; u < NT; ++u) {
+            const int tap = t0 + u * 64 + lane;
+            ok[u] = tap < SS;
+            txs[u] = tx;
+            tys[u] = ty;
+            // every lane loads (a lane past the footprint reads tap 0, in
+            // bounds, and adds nothing): loads outside divergent branches
+            // let the waits count down tap by tap
+            const uint32_t co = ok[u] ? (uint32_t)tap * (uint32_t)E : 0u;
+            const uint32_t go = ok[u] ? (uint32_t)goff : 0u;
+            cr[u] = *(const Raw *)(cfb + co);
+            for (int p = 0; p < NPOL; ++p) {
+                const T *q = (const T *)(gbp[p] + go);
+                gv[u][p] = {q[0], q[1]};
+            }
+            // advance by 64 taps
+            tx += dtx;
+            ty += dty;
+            goff += dty * row + dtx * (int)(2 * sizeof(T));
+            if (tx >= S) {
+                tx -= S;
+                ++ty;
+                goff += row - S * (int)(2 * sizeof(T));
+            }
+        }
+        for (int u = 0; u < NT; ++u) {
+            if constexpr (RE) {
+                const T c = ok[u] ? CFReal<ST>::decode(cr[u], sc) : (T)0;
+                for (int p = 0; p < NPOL; ++p) {
+                    sum[p].x = fma(c, gv[u][p].x, sum[p].x);
+                    sum[p].y = fma(c, gv[u][p].y, sum[p].y);
+                }
+            } else {
+                cpx<T> cv = CFRaw<ST>::decode(cr[u], sc);
+                if (!ok[u]) cv = {(T)0, (T)0};
+                if (cj) cv.y = -cv.y;
+                if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
+                for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
+            }
+        }
+    }
+    cpx<T> *out = (cpx<T> *)a.Vg;
+    for (int p = 0; p < NPOL; ++p) {
+        T x = wave_sum(sum[p].x), y = wave_sum(sum[p].y);
+        if (lane == 0) out[g * NPOL + p] = {x, y};
+    }
+}
+
+// Small supports (S <= 2 kDegridSmallH + 1): a 7 x 7 footprint would leave
+// most of a wavefront idle, so 16 lanes take one group (four groups per
+// wavefront), four taps per lane in flight, and reduce over their 16 lanes.
+constexpr int kDegridSmallH = 7;
+
+template <typename T, int ST, int NPOL, bool PO, bool RE>
+__global__ __launch_bounds__(256) void k_degrid_small(DegridArgs a) {
+    constexpr int E = CFRaw<ST>::bytes;
+    typedef typename std::conditional<RE, typename CFReal<ST>::R, typename CFRaw<ST>::R>::type Raw;
+    const int sub = threadIdx.x & 15;
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
+    const bool live = g < a.n_groups;
+    cpx<T> sum[NPOL];
+    for (int p = 0; p < NPOL; ++p) sum[p] = {(T)0, (T)0};
+    if (live) {
+        const GroupMeta gm = a.groups[g];
+        const int h = gm.h;
+        const int S = 2 * h + 1;
+        const int SS = S * S;
+        const float invS = 1.0f / (float)S;
+        const char *cfb = (const char *)a.cf.table + gm.cf_off * E;
+        const int64_t corner = gm.cell - (int64_t)h * a.nx - h;
+        const T *grid = (const T *)a.grid;
+        for (int t0 = 0; t0 < SS; t0 += 64) {
+            Raw cr[4];
+            cpx<T> gv[4][NPOL];
+            int tys[4], txs[4];
+            for (int u = 0; u < 4; ++u) {
+                const int tap = t0 + u * 16 + sub;
+                int ty, tx;
+                divmod_small(tap, S, invS, ty, tx);
+                tys[u] = ty;
+                txs[u] = tx;
+                // every lane loads (past the footprint: tap 0, in bounds,
+                // adding nothing), outside divergent branches
+                const bool in = tap < SS;
+                const int64_t cell = in ? corner + (int64_t)ty * a.nx + tx : corner;
+                cr[u] = *(const Raw *)(cfb + (in ? (int64_t)tap * E : 0));
+                for (int p = 0; p < NPOL; ++p) {
+                    const T *q = grid + 2 * (cell + p * a.pol_stride);
+                    gv[u][p] = {q[0], q[1]};
+                }
+            }
+            for (int u = 0; u < 4; ++u) {
+                const bool in = t0 + u * 16 + sub < SS;
+                if constexpr (RE) {
+                    const T c = in ? CFReal<ST>::decode(cr[u], gm.sc) : (T)0;
+                    for (int p = 0; p < NPOL; ++p) {
+                        sum[p].x = fma(c, gv[u][p].x, sum[p].x);
+                        sum[p].y = fma(c, gv[u][p].y, sum[p].y);
+                    }
+                } else {
+                    cpx<T> cv = CFRaw<ST>::decode(cr[u], gm.sc);
+                    if (!in) cv = {(T)0, (T)0};
+                    if (gm.conj) cv.y = -cv.y;
+                    if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
+                    for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
+                }
+            }
+        }
+    }
+    for (int p = 0; p < NPOL; ++p)
+        for (int off = 8; off > 0; off >>= 1) {
+            sum[p].x += __shfl_xor(sum[p].x, off);
+            sum[p].y += __shfl_xor(sum[p].y, off);
+        }
+    if (live && sub == 0) {
+        cpx<T> *out = (cpx<T> *)a.Vg;
+        for (int p = 0; p < NPOL; ++p) out[g * NPOL + p] = sum[p];
+    }
+}
+
+template <typename T, int ST, int NPOL>
+static hipError_t degrid_t(const DegridArgs &da, bool po, bool small, hipStream_t s) {
+    dim3 blk(256);
+    const bool re = !po && da.cf.real;
+    if (small) {
+        dim3 grd(nblk(da.n_groups, 16));
+        if (po) hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, true, false>), grd, blk, 0, s, da);
+        else if (re) hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, false, true>), grd, blk, 0, s, da);
+        else hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, false, false>), grd, blk, 0, s, da);
+        return hipGetLastError();
+    }
+    dim3 grd(nblk(da.n_groups, 4));
+    if (po) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, true, false>), grd, blk, 0, s, da);
+    else if (re) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false, true>), grd, blk, 0, s, da);
+    else hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false, false>), grd, blk, 0, s, da);
+    return hipGetLastError();
+}
+
+template <typename T, int ST>
+static hipError_t degrid_np(const DegridArgs &da, int npol, bool po, bool small,
+                            hipStream_t s) {
+    switch (npol) {
+        case 1: return degrid_t<T, ST, 1>(da, po, small, s);
+        case 2: return degrid_t<T, ST, 2>(da, po, small, s);
+        default: return degrid_t<T, ST, 4>(da, po, small, s);
+    }
+}
+
+hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
+                         int precision, int32_t npol, int32_t nx, int32_t ny, int32_t h_max,
+                         hipStream_t s) {
+    if (P->n_groups == 0) return hipSuccess;
+    DegridArgs da{P->groups, P->n_groups, grid, Vg, cf, nx, ny, (int64_t)nx * ny};
+    bool po = P->po != 0;
+    bool sm = h_max <= kDegridSmallH;
+    switch (precision) {
+        case LR_F64: return degrid_np<double, LR_F64>(da, npol, po, sm, s);
+        case LR_F32: return degrid_np<float, LR_F32>(da, npol, po, sm, s);
+        case LR_F32_CF16: return degrid_np<float, LR_F32_CF16>(da, npol, po, sm, s);
+        default: return degrid_np<float, LR_F32_CFBF16>(da, npol, po, sm, s);
+    }
+}
+
+}  // namespace lr

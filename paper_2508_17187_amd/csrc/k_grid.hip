@@ -1,7 +1,5 @@
-// The gridding / degridding hot path on gfx950 (no MFMA: the work is a
-// scatter / gather, not a dense contraction).
-//
-// Gridding G (Eq. IMAGE-MOD) runs in two kernels over a binning plan:
+// Gridding G (Eq. IMAGE-MOD) on gfx950 (no MFMA: the work is a scatter /
+// gather, not a dense contraction), over a binning plan:
 //   presum   for every group of samples that share plane, kernel and
 //            footprint, A_g = sum W V (exact regrouping of the sum; FP32 or
 //            FP64), together with the class counters and FP64 sum of weights;
@@ -11,12 +9,11 @@
 //            registers; the tile is written once at the end, with plain loads
 //            and stores when the chunk owns the whole tile.  Group data are
 //            workgroup-uniform (scalar loads); a kernel tap is one vector load.
-// Degridding D (Eq. ME-MOD-GRIDDED):
-//   degrid   one wavefront per group gathers sum_t conj(Ct phi) grid over the
-//            footprint (lanes over taps, coalesced along t_u) and reduces
-//            across lanes;
-//   expand   writes each group's value to every sample of the group (0 for
-//            flagged, skipped and dropped samples).
+//            Separable kernels of small support take the LDS-tile gridder of
+//            k_sep.hip instead.
+// The degridder's second half lives here too:
+//   expand   writes each group's value (k_degrid.hip) to every sample of the
+//            group (0 for flagged, skipped and dropped samples).
 #include <stdlib.h>
 #include <string.h>
 
@@ -25,72 +22,9 @@
 
 #include "lr_internal.h"
 #include "lr_launch.h"
+#include "k_common.h"
 
 namespace lr {
-
-template <typename T>
-struct cpx {
-    T x, y;
-};
-
-// Per-sample records (npol values) moved in 16-byte pieces when their size
-// allows: callers pass pointers to whole records, which are 16-byte aligned
-// whenever the record size is a multiple of 16.
-template <typename E, int N>
-__device__ __forceinline__ void vload(const E *p, E (&out)[N]) {
-    if constexpr ((N * sizeof(E)) % 16 == 0) {
-        const E *q = (const E *)__builtin_assume_aligned(p, 16);
-        __builtin_memcpy(out, q, N * sizeof(E));
-    } else {
-        for (int i = 0; i < N; ++i) out[i] = p[i];
-    }
-}
-
-template <typename E, int N>
-__device__ __forceinline__ void vstore(E *p, const E (&in)[N]) {
-    if constexpr ((N * sizeof(E)) % 16 == 0) {
-        E *q = (E *)__builtin_assume_aligned(p, 16);
-        __builtin_memcpy(q, in, N * sizeof(E));
-    } else {
-        for (int i = 0; i < N; ++i) p[i] = in[i];
-    }
-}
-
-// Streaming (nontemporal) moves of FP32 records that are read or written
-// once per call (the visibilities and weights in the presum and expand
-// passes), so they do not displace the grid, table and group data the
-// other kernels reuse from cache.  FP64 records take the ordinary path:
-// measured slower with streaming stores on this chip.
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-template <typename E>
-constexpr bool kStream = std::is_same<E, float>::value || std::is_same<E, cpx<float>>::value;
-
-template <typename E, int N>
-__device__ __forceinline__ void sload(const E *p, E (&out)[N]) {
-    if constexpr ((N * sizeof(E)) % 16 == 0 && kStream<E>) {
-        constexpr int K = N * sizeof(E) / 16;
-        f32x4 t[K];
-        const f32x4 *q = (const f32x4 *)__builtin_assume_aligned(p, 16);
-        for (int i = 0; i < K; ++i) t[i] = __builtin_nontemporal_load(q + i);
-        __builtin_memcpy(out, t, N * sizeof(E));
-    } else {
-        vload(p, out);
-    }
-}
-
-template <typename E, int N>
-__device__ __forceinline__ void sstore(E *p, const E (&in)[N]) {
-    if constexpr ((N * sizeof(E)) % 16 == 0 && kStream<E>) {
-        constexpr int K = N * sizeof(E) / 16;
-        f32x4 t[K];
-        __builtin_memcpy(t, in, N * sizeof(E));
-        f32x4 *q = (f32x4 *)__builtin_assume_aligned(p, 16);
-        for (int i = 0; i < K; ++i) __builtin_nontemporal_store(t[i], q + i);
-    } else {
-        vstore(p, in);
-    }
-}
-
 __global__ void k_zero(uint4 *p, int64_t n16, uint8_t *tail, int ntail) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n16) p[i] = make_uint4(0, 0, 0, 0);
@@ -105,183 +39,6 @@ hipError_t launch_zero(void *p, size_t bytes, hipStream_t s) {
     hipLaunchKernelGGL(k_zero, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (uint4 *)p,
                        n16, (uint8_t *)p + n16 * 16, ntail);
     return hipGetLastError();
-}
-
-// ---------------------------------------------------------------------------
-// CF element access; f16 / bf16 pairs are decoded exactly to FP32 and
-// multiplied by the plane's 2^-e.
-template <int ST>
-struct CFElem;
-template <>
-struct CFElem<LR_F64> {
-    typedef double T;
-    __device__ static cpx<double> load(const void *t, int64_t i, float) {
-        double2 v = ((const double2 *)t)[i];
-        return {v.x, v.y};
-    }
-};
-template <>
-struct CFElem<LR_F32> {
-    typedef float T;
-    __device__ static cpx<float> load(const void *t, int64_t i, float) {
-        float2 v = ((const float2 *)t)[i];
-        return {v.x, v.y};
-    }
-};
-template <>
-struct CFElem<LR_F32_CF16> {
-    typedef float T;
-    __device__ static cpx<float> load(const void *t, int64_t i, float sc) {
-        uint32_t b = ((const uint32_t *)t)[i];
-        _Float16 lo, hi;
-        uint16_t l16 = (uint16_t)(b & 0xffffu), h16 = (uint16_t)(b >> 16);
-        __builtin_memcpy(&lo, &l16, 2);
-        __builtin_memcpy(&hi, &h16, 2);
-        return {(float)lo * sc, (float)hi * sc};
-    }
-};
-template <>
-struct CFElem<LR_F32_CFBF16> {
-    typedef float T;
-    __device__ static cpx<float> load(const void *t, int64_t i, float sc) {
-        uint32_t b = ((const uint32_t *)t)[i];
-        return {__uint_as_float(b << 16) * sc, __uint_as_float(b & 0xffff0000u) * sc};
-    }
-};
-
-// Raw storage words of one CF element, loaded from a byte address and
-// decoded later, so that a batch of loads is in flight before any value is
-// needed.
-template <int ST>
-struct CFRaw;
-template <>
-struct CFRaw<LR_F64> {
-    typedef double2 R;
-    static constexpr int bytes = 16;
-    __device__ static cpx<double> decode(R v, float) { return {v.x, v.y}; }
-};
-template <>
-struct CFRaw<LR_F32> {
-    typedef float2 R;
-    static constexpr int bytes = 8;
-    __device__ static cpx<float> decode(R v, float) { return {v.x, v.y}; }
-};
-template <>
-struct CFRaw<LR_F32_CF16> {
-    typedef uint32_t R;
-    static constexpr int bytes = 4;
-    __device__ static cpx<float> decode(R b, float sc) {
-        _Float16 lo, hi;
-        uint16_t l16 = (uint16_t)(b & 0xffffu), h16 = (uint16_t)(b >> 16);
-        __builtin_memcpy(&lo, &l16, 2);
-        __builtin_memcpy(&hi, &h16, 2);
-        return {(float)lo * sc, (float)hi * sc};
-    }
-};
-template <>
-struct CFRaw<LR_F32_CFBF16> {
-    typedef uint32_t R;
-    static constexpr int bytes = 4;
-    __device__ static cpx<float> decode(R b, float sc) {
-        return {__uint_as_float(b << 16) * sc, __uint_as_float(b & 0xffff0000u) * sc};
-    }
-};
-
-// Real tables (no A term, no w-dependence): only the real word of each
-// stored pair is loaded, and a tap costs two FMAs per polarisation instead
-// of four (the imaginary parts are rounding noise, below 1e-16 relative).
-template <int ST>
-struct CFReal;
-template <>
-struct CFReal<LR_F64> {
-    typedef double R;
-    __device__ static double decode(R v, float) { return v; }
-};
-template <>
-struct CFReal<LR_F32> {
-    typedef float R;
-    __device__ static float decode(R v, float) { return v; }
-};
-template <>
-struct CFReal<LR_F32_CF16> {
-    typedef uint16_t R;
-    __device__ static float decode(R b, float sc) {
-        _Float16 x;
-        __builtin_memcpy(&x, &b, 2);
-        return (float)x * sc;
-    }
-};
-template <>
-struct CFReal<LR_F32_CFBF16> {
-    typedef uint16_t R;
-    __device__ static float decode(R b, float sc) { return __uint_as_float((uint32_t)b << 16) * sc; }
-};
-
-// Wave-uniform copies of values that are the same in every lane.
-__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ int64_t uni64(int64_t v) {
-    const uint32_t lo = (uint32_t)uni((int)(uint32_t)v);
-    const uint32_t hi = (uint32_t)uni((int)(uint32_t)((uint64_t)v >> 32));
-    return (int64_t)(((uint64_t)hi << 32) | lo);
-}
-
-template <typename T>
-__device__ __forceinline__ void cmac(cpx<T> &acc, const cpx<T> &c, const cpx<T> &a) {
-    acc.x = fma(c.x, a.x, acc.x);
-    acc.x = fma(-c.y, a.y, acc.x);
-    acc.y = fma(c.x, a.y, acc.y);
-    acc.y = fma(c.y, a.x, acc.y);
-}
-
-// conj(c) * g accumulated
-template <typename T>
-__device__ __forceinline__ void cmac_conj(cpx<T> &acc, const cpx<T> &c, const cpx<T> &g) {
-    acc.x = fma(c.x, g.x, acc.x);
-    acc.x = fma(c.y, g.y, acc.x);
-    acc.y = fma(c.x, g.y, acc.y);
-    acc.y = fma(-c.y, g.x, acc.y);
-}
-
-// Pointing phasor of tap (tu, tv): f exp(-2 pi i ((tu O - ou) bu + (tv O - ov) bv)),
-// argument formed and reduced modulo 1 in FP64.
-template <typename T>
-__device__ __forceinline__ cpx<T> phasor(const GroupMeta &gm, int tu, int tv, int O) {
-    double a = fma((double)(tu * O - gm.ou), gm.bu, (double)(tv * O - gm.ov) * gm.bv);
-    a = a - rint(a);
-    cpx<T> r;
-    if (sizeof(T) == 8) {
-        double s, c;
-        sincospi(-2.0 * a, &s, &c);
-        r.x = (T)(gm.f * c);
-        r.y = (T)(gm.f * s);
-    } else {
-        float s, c;
-        sincospif((float)(-2.0 * a), &s, &c);
-        r.x = (T)((float)gm.f * c);
-        r.y = (T)((float)gm.f * s);
-    }
-    return r;
-}
-
-template <typename T>
-__device__ __forceinline__ cpx<T> cmul(const cpx<T> &a, const cpx<T> &b) {
-    cpx<T> r;
-    r.x = a.x * b.x - a.y * b.y;
-    r.y = a.x * b.y + a.y * b.x;
-    return r;
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-__device__ __forceinline__ double wave_sum(double v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-__device__ __forceinline__ long long wave_sum_ll(long long v) {
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
 }
 
 // ---------------------------------------------------------------------------
@@ -631,19 +388,9 @@ struct TileItem {
     int32_t h;
 };
 
-// Exact t / S and t % S for 0 <= t < 2^22 through a float reciprocal.
-__device__ __forceinline__ void divmod_small(int t, int S, float invS, int &q, int &r) {
-    q = (int)(((float)t + 0.5f) * invS);
-    r = t - q * S;
-    if (r < 0) { --q; r += S; } else if (r >= S) { ++q; r -= S; }
-}
-
 // Items a wavefront takes per step: their kernel loads are in flight
 // together.
 constexpr int kItemBatch = 4;
-// s_waitcnt operand for vmcnt(0) with the other counters left alone
-// (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
-constexpr int kWaitVm0 = 0x0F70;
 // items of a chunk as ballot bits, 64 per word
 constexpr int kMaskWords = (kChunkMax + 63) / 64;
 
@@ -833,361 +580,6 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
     }
 }
 
-// ---------------------------------------------------------------------------
-// Gridder for separable kernels of small support (the Standard kernel: PS
-// only, one plane, S = 2h + 1 <= 15).  One workgroup owns one 32 x 32 tile:
-// it accumulates the tile in LDS and writes it to the grid once, so no cell
-// is updated twice in global memory and no atomics reach the grid.
-//
-// CF cache: a separable plane is an outer product, C[o_v][o_u][t_v][t_u] =
-// cv[o_v][t_v] cu[o_u][t_u] with cu the o_v = 0, t_v = 0 row and cv the
-// o_u = 0, t_u = 0 column over the centre tap.  The workgroup derives both
-// factor tables ((O + 1) S values each) from the stored plane into LDS, so
-// no tap is read from global memory.
-//
-// Each wavefront owns a band of kSepBand tile rows and is the only one to
-// touch them in LDS, so its adds are plain read-modify-writes (LDS float
-// atomics, which every wavefront of the tile would otherwise need, cost
-// four times the rest of the kernel on one-sample groups).  The plan sorts
-// a tile's pairs by pixel row, so the pairs whose footprints meet a band
-// are one contiguous range, found by a wavefront-wide search; a pair whose
-// footprint spans two bands is gridded by both wavefronts, each keeping
-// its own rows.  The wavefront takes its range in blocks of 16 (lane l
-// holds pair l & 15; the loads of the next block are in flight while one
-// is gridded), one pair at a time with lanes over taps: lane t adds cu cv
-// A[pol] into registers for tap t (and t + 64, ... for S > 7).  Pairs of
-// one pixel (same footprint) follow each other; the registers are added to
-// the band when the pixel changes.
-struct SepArgs {
-    const int32_t *tp_group;
-    const int32_t *tile_tp;
-    const int4 *part;         // (tile, first pair, end pair, several parts)
-    int32_t n_parts;
-    const int64_t *geo;
-    const void *A;
-    void *grid;
-    const void *table;        // element 0 of plane (0, 0)
-    const float *scale;       // 2^-e of plane (0, 0)
-    int32_t O, h;
-    int32_t nx, ny, ntx, nty;
-    int64_t pol_stride;
-    int32_t set;              // GRID_SET: every cell written (0 where nothing lands)
-};
-
-constexpr int kSepBlock = 16;
-
-template <typename T>
-__device__ __forceinline__ T lane_value(T v, int j) {
-    if constexpr (sizeof(T) == 4) {
-        return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), j));
-    } else {
-        const int lo = __builtin_amdgcn_readlane(__double2loint(v), j);
-        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), j);
-        return __hiloint2double(hi, lo);
-    }
-}
-
-// FP32 broadcasts: lanes 16 r + J of every row of 16 lanes hold the same
-// value (the block's pair J), and the DPP row_newbcast:J operand hands it to
-// every lane of the row, so a pair's values reach all lanes with no
-// instruction of their own.  A DPP read needs two wait states after a VALU
-// write of its source register (s_nop 1).
-// acc[p] += A[p] of the block's pair J times t, for the NPOL complex values
-// of one cell, in one block: a single s_nop 1 covers every DPP source (no
-// instruction inside the block writes one; the accumulators are not DPP
-// operands).
-#define LR_FMAC_DPP(d, v) "v_fmac_f32_dpp %" #d ", %" #v ", %[t] row_newbcast:%[j] row_mask:0xf bank_mask:0xf\n\t"
-template <int J, int NPOL>
-__device__ __forceinline__ void fmac_bcast_cell(cpx<float> *acc, const cpx<float> *av, float t) {
-    if constexpr (NPOL == 4) {
-        asm("s_nop 1\n\t" LR_FMAC_DPP(0, 8) LR_FMAC_DPP(1, 9) LR_FMAC_DPP(2, 10)
-            LR_FMAC_DPP(3, 11) LR_FMAC_DPP(4, 12) LR_FMAC_DPP(5, 13) LR_FMAC_DPP(6, 14)
-            LR_FMAC_DPP(7, 15)
-            : "+v"(acc[0].x), "+v"(acc[0].y), "+v"(acc[1].x), "+v"(acc[1].y), "+v"(acc[2].x),
-              "+v"(acc[2].y), "+v"(acc[3].x), "+v"(acc[3].y)
-            : "v"(av[0].x), "v"(av[0].y), "v"(av[1].x), "v"(av[1].y), "v"(av[2].x),
-              "v"(av[2].y), "v"(av[3].x), "v"(av[3].y), [t] "v"(t), [j] "n"(J));
-    } else if constexpr (NPOL == 2) {
-        asm("s_nop 1\n\t" LR_FMAC_DPP(0, 4) LR_FMAC_DPP(1, 5) LR_FMAC_DPP(2, 6) LR_FMAC_DPP(3, 7)
-            : "+v"(acc[0].x), "+v"(acc[0].y), "+v"(acc[1].x), "+v"(acc[1].y)
-            : "v"(av[0].x), "v"(av[0].y), "v"(av[1].x), "v"(av[1].y), [t] "v"(t), [j] "n"(J));
-    } else {
-        asm("s_nop 1\n\t" LR_FMAC_DPP(0, 2) LR_FMAC_DPP(1, 3)
-            : "+v"(acc[0].x), "+v"(acc[0].y)
-            : "v"(av[0].x), "v"(av[0].y), [t] "v"(t), [j] "n"(J));
-    }
-}
-#undef LR_FMAC_DPP
-template <int J>
-__device__ __forceinline__ float bcast(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + J, 0xF, 0xF, true));
-}
-template <int J>
-__device__ __forceinline__ int bcast(int v) {
-    return __builtin_amdgcn_mov_dpp(v, 0x150 + J, 0xF, 0xF, true);
-}
-
-// f(integral_constant<int, J>) for J = 0 .. N - 1, in order.
-template <int J, int N, typename F>
-__device__ __forceinline__ void for_const(F &&f) {
-    f(std::integral_constant<int, J>{});
-    if constexpr (J + 1 < N) for_const<J + 1, N>(f);
-}
-
-constexpr int kSepBand = 8;                       // tile rows per wavefront
-constexpr int kSepThreads = 64 * (kTile / kSepBand);
-
-// First index i in [lo, hi) whose pair's pixel row is >= key (hi if none),
-// the rows ascending over the range: 64 samples per round, so a part of
-// up to 4096 pairs takes two rounds.  Wave-uniform result.
-__device__ __forceinline__ int band_bound(const int32_t *tp_group, const int64_t *geo, int lo,
-                                          int hi, int key, int lane) {
-    while (lo < hi) {
-        const int step = (hi - lo + 63) / 64;
-        const int i = lo + lane * step;
-        bool ge = true;                                   // past the end counts as >= key
-        if (i < hi) ge = (int)((geo[tp_group[i]] >> 16) & 0xFFFF) >= key;
-        const uint64_t m = __ballot(ge);
-        if (m == 0) {
-            lo += 63 * step + 1;
-            continue;
-        }
-        const int c = __builtin_ctzll(m);
-        if (c == 0) return lo;
-        hi = min(hi, lo + c * step);
-        lo += (c - 1) * step + 1;
-    }
-    return lo;
-}
-
-template <typename T, int ST, int NPOL, int NT>
-__global__ __launch_bounds__(kSepThreads) void k_grid_sep(SepArgs a) {
-    constexpr int E = CFRaw<ST>::bytes;
-    typedef typename CFReal<ST>::R Raw;
-    constexpr int NC = 2 * NPOL;              // values per cell
-    constexpr int RS = kTile * NC + 1;        // LDS row stride: rows start one bank apart
-    __shared__ T tl[kTile * RS];
-    extern __shared__ __align__(16) char cf_lds[];
-    // workgroups take the parts (heaviest tiles first); those after the
-    // parts write the tiles without pairs as zeros (GRID_SET)
-    int tile, b0, b1, shared = 0;
-    if ((int)blockIdx.x < a.n_parts) {
-        const int4 pt = a.part[blockIdx.x];
-        tile = pt.x;
-        b0 = pt.y;
-        b1 = pt.z;
-        shared = pt.w;
-    } else {
-        tile = (int)blockIdx.x - a.n_parts;
-        b0 = b1 = 0;
-        if (a.tile_tp[tile] != a.tile_tp[tile + 1]) return;
-    }
-    const int tx = tile % a.ntx;
-    const int rest = tile / a.ntx;
-    const int ty = rest % a.nty;
-    const int P = rest / a.nty;
-    const int x0 = tx * kTile, y0 = ty * kTile;
-    T *grid = (T *)a.grid;
-    const int lane = threadIdx.x & 63;
-    if (b0 == b1) {
-        // no pairs: under GRID_SET the tile is written as zeros
-        if (!a.set) return;
-        for (int i = threadIdx.x; i < kTile * kTile * NPOL; i += blockDim.x) {
-            const int p = i % NPOL, c = i / NPOL;
-            const int x = x0 + c % kTile, y = y0 + c / kTile;
-            if (x < a.nx && y < a.ny) {
-                T *q = grid + 2 * (((int64_t)P * NPOL + p) * a.pol_stride + (int64_t)y * a.nx + x);
-                q[0] = (T)0;
-                q[1] = (T)0;
-            }
-        }
-        return;
-    }
-    const int h = a.h, S = 2 * h + 1, O = a.O, no = O + 1, half = O >> 1;
-    T *cu = (T *)cf_lds;
-    T *cv = cu + no * S;
-    // this wavefront's band and the pairs whose footprints meet it (the
-    // search's loads overlap the factor tables' build)
-    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int yb = wv * kSepBand;
-    const int r0 = band_bound(a.tp_group, a.geo, b0, b1, y0 + yb - h, lane);
-    const int r1 = band_bound(a.tp_group, a.geo, r0, b1, y0 + yb + kSepBand + h, lane);
-    {
-        const char *tb = (const char *)a.table;
-        const float sc = a.scale[0];
-        auto ent = [&](int ovi, int oui, int tvi, int tui) {
-            const int64_t e = (((int64_t)ovi * no + oui) * S + tvi) * S + tui;
-            return (T)CFReal<ST>::decode(*(const Raw *)(tb + e * E), sc);
-        };
-        const T centre = ent(half, half, h, h);
-        for (int i = threadIdx.x; i < no * S; i += blockDim.x) {
-            const int o = i / S, t = i - o * S;
-            cu[i] = ent(half, o, h, t);
-            cv[i] = ent(o, half, t, h) / centre;
-        }
-        for (int i = threadIdx.x; i < kTile * RS; i += blockDim.x) tl[i] = (T)0;
-    }
-    __syncthreads();
-    // this lane's taps t = lane + 64 n: (tv, tu) and whether t < S^2
-    int tu[NT], tv[NT];
-    bool tin[NT];
-    for (int n = 0; n < NT; ++n) {
-        const int t = lane + 64 * n;
-        tv[n] = t / S;
-        tu[n] = t - tv[n] * S;
-        tin[n] = t < S * S;
-        if (!tin[n]) tu[n] = tv[n] = 0;
-    }
-    const int nb = (r1 - r0 + kSepBlock - 1) / kSepBlock;
-    const cpx<T> *Av = (const cpx<T> *)a.A;
-    // the band cells under the current run's footprint, in registers: read
-    // from LDS when the run's pixel starts, written back when it ends (the
-    // lane's tap is the cell; lanes outside the band or the tile keep
-    // theirs out of LDS)
-    cpx<T> acc[NT][NPOL];
-    bool in[NT];
-    int loff[NT], addr[NT];
-    for (int n = 0; n < NT; ++n) {
-        loff[n] = tv[n] * RS + tu[n] * NC;
-        addr[n] = 0;
-        in[n] = false;
-        for (int p = 0; p < NPOL; ++p) acc[n][p] = {(T)0, (T)0};
-    }
-    int cur = -1;            // packed pixel of the run in the registers (wave-uniform)
-    auto store_run = [&]() {
-        for (int n = 0; n < NT; ++n) {
-            if (in[n]) {
-                T *c = tl + addr[n];
-                for (int p = 0; p < NPOL; ++p) {
-                    c[2 * p] = acc[n][p].x;
-                    c[2 * p + 1] = acc[n][p].y;
-                }
-            }
-        }
-    };
-    auto load_run = [&](int pj) {
-        const int px = (pj & 0xFFFF) - h - x0, py = (pj >> 16) - h - y0;
-        const int base = py * RS + px * NC;
-        for (int n = 0; n < NT; ++n) {
-            in[n] = tin[n] && (unsigned)(px + tu[n]) < (unsigned)kTile &&
-                    (unsigned)(py + tv[n] - yb) < (unsigned)kSepBand;
-            addr[n] = base + loff[n];
-            if (in[n]) {
-                const T *c = tl + addr[n];
-                for (int p = 0; p < NPOL; ++p) acc[n][p] = {c[2 * p], c[2 * p + 1]};
-            }
-        }
-    };
-    // block loads: group, geometry and group sums of pair (l & 15)
-    struct Blk {
-        int64_t geo;
-        cpx<T> av[NPOL];
-    };
-    auto load_group = [&](int blk) {
-        const int i = r0 + blk * kSepBlock + (lane & (kSepBlock - 1));
-        return i < r1 ? a.tp_group[i] : -1;
-    };
-    auto load_blk = [&](int g, Blk &d) {
-        if (g >= 0) {
-            d.geo = a.geo[g];
-            vload(Av + (int64_t)g * NPOL, d.av);
-        } else {
-            d.geo = 0;
-            for (int p = 0; p < NPOL; ++p) d.av[p] = {(T)0, (T)0};
-        }
-    };
-    int g_next = 1 < nb ? load_group(1) : -1;
-    Blk cb;
-    if (nb > 0) load_blk(load_group(0), cb);
-    for (int blk = 0; blk < nb; ++blk) {
-        // the next block's sums and geometry, and the group ids of the one
-        // after, are loaded while this block is gridded
-        Blk nbk;
-        if (blk + 1 < nb) load_blk(g_next, nbk);
-        const int g_after = blk + 2 < nb ? load_group(blk + 2) : -1;
-        const int cnt = min(kSepBlock, r1 - (r0 + blk * kSepBlock));
-        // per-pair base addresses of the factor tables
-        const int ou = (int)(int16_t)(cb.geo >> 32), ov = (int)(int16_t)(cb.geo >> 48);
-        const int pix = (int)(cb.geo & 0xFFFFFFFF);
-        const int ub = (ou + half) * S, vb = (ov + half) * S;
-        // this lane's taps of every pair of the block, all LDS reads in
-        // flight before the first is used
-        T tp[kSepBlock][NT], tq[kSepBlock][NT];
-        for_const<0, kSepBlock>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            int ubj, vbj;
-            if constexpr (sizeof(T) == 4) {
-                ubj = bcast<j>(ub);
-                vbj = bcast<j>(vb);
-            } else {
-                ubj = __builtin_amdgcn_readlane(ub, j);
-                vbj = __builtin_amdgcn_readlane(vb, j);
-            }
-            for (int n = 0; n < NT; ++n) {
-                tp[j][n] = cu[ubj + tu[n]];
-                tq[j][n] = cv[vbj + tv[n]];
-            }
-        });
-        // every factor read is issued before any is used (the compiler would
-        // otherwise wait for each pair's reads in turn), then the taps
-        for (int j = 0; j < kSepBlock; ++j)
-            for (int n = 0; n < NT; ++n) asm volatile("" : "+v"(tp[j][n]), "+v"(tq[j][n]));
-        for (int j = 0; j < kSepBlock; ++j)
-            for (int n = 0; n < NT; ++n) tp[j][n] *= tq[j][n];
-        for_const<0, kSepBlock>([&](auto jc) {
-            constexpr int j = decltype(jc)::value;
-            if (j >= cnt) return;
-            const int pj = __builtin_amdgcn_readlane(pix, j);
-            if (pj != __builtin_amdgcn_readfirstlane(cur)) {
-                if (cur >= 0) store_run();
-                load_run(pj);
-                cur = pj;
-            }
-            for (int n = 0; n < NT; ++n) {
-                const T tap = tp[j][n];
-                if constexpr (sizeof(T) == 4) {
-                    fmac_bcast_cell<j, NPOL>(acc[n], cb.av, tap);
-                } else {
-                    for (int p = 0; p < NPOL; ++p) {
-                        const T ax = lane_value(cb.av[p].x, j), ay = lane_value(cb.av[p].y, j);
-                        acc[n][p].x = fma(tap, ax, acc[n][p].x);
-                        acc[n][p].y = fma(tap, ay, acc[n][p].y);
-                    }
-                }
-            }
-        });
-        cb = nbk;
-        g_next = g_after;
-    }
-    if (cur >= 0) store_run();
-    // write the band (only this wavefront wrote it, so no barrier): lane
-    // pairs (cell, pol) with pol fastest, so LDS reads are consecutive and
-    // each pol's cells are 16 consecutive grid values
-    constexpr int CPI = 64 / NPOL;                 // cells per wavefront step
-    for (int c0 = 0; c0 < kSepBand * kTile; c0 += CPI) {
-        const int c = c0 + lane / NPOL, p = lane % NPOL;
-        const int xl = c % kTile, yl = yb + c / kTile;
-        const int x = x0 + xl, y = y0 + yl;
-        if (x >= a.nx || y >= a.ny) continue;
-        const T *src = tl + yl * RS + xl * NC + 2 * p;
-        const T vx = src[0], vy = src[1];
-        T *q = grid + 2 * (((int64_t)P * NPOL + p) * a.pol_stride + (int64_t)y * a.nx + x);
-        if (shared) {
-            // a tile split into several parts: every part adds its share
-            if (vx != (T)0 || vy != (T)0) {
-                atomicAdd(q, vx);
-                atomicAdd(q + 1, vy);
-            }
-        } else if (a.set) {
-            q[0] = vx;
-            q[1] = vy;
-        } else if (vx != (T)0 || vy != (T)0) {
-            q[0] += vx;
-            q[1] += vy;
-        }
-    }
-}
-
 // Set-up of a gridding call in one launch: the first n_shared workgroups
 // clear the shared tiles (GRID_SET), the rest zero up to three word spans
 // (group sums, sums of weights, counters), four 8-byte words per thread.
@@ -1232,179 +624,6 @@ __global__ __launch_bounds__(256) void k_grid_setup(SetupArgs a) {
             }
             r -= a.zw[k];
         }
-    }
-}
-
-// ---------------------------------------------------------------------------
-struct DegridArgs {
-    const GroupMeta *groups;
-    int64_t n_groups;
-    const void *grid;
-    void *Vg;
-    CFView cf;
-    int32_t nx, ny;
-    int64_t pol_stride;
-};
-
-// Taps per lane whose loads are in flight together in the degridder: 4, or
-// 8 with 4-byte (FP16 / BF16) kernel values, whose raw words take half the
-// registers.
-constexpr int kDegridTaps = 4;
-
-// One wavefront per group: lanes walk the footprint taps in row-major order,
-// four or eight taps per lane in flight; the sub-kernel and the footprint's
-// corner cell (per pol) are scalar base addresses and a lane carries 32-bit
-// offsets, advanced by 64 taps at a time without division.
-template <typename T, int ST, int NPOL, bool PO, bool RE>
-__global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
-    constexpr int E = CFRaw<ST>::bytes;
-    constexpr int NT = E <= 4 ? 2 * kDegridTaps : kDegridTaps;
-    typedef typename std::conditional<RE, typename CFReal<ST>::R, typename CFRaw<ST>::R>::type Raw;
-    const int lane = threadIdx.x & 63;
-    // consecutive groups (same plane, neighbouring footprints) run side by
-    // side across the XCDs, which share the last-level cache
-    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + uni(threadIdx.x >> 6);
-    if (g >= a.n_groups) return;
-    const GroupMeta gm = a.groups[g];
-    const int h = uni(gm.h);
-    const int S = 2 * h + 1;
-    const int SS = S * S;
-    const float sc = gm.sc;
-    const bool cj = uni(gm.conj) != 0;
-    const char *cfb = (const char *)a.cf.table + uni64(gm.cf_off) * E;
-    // corner cell (tap (0, 0)) of pol 0
-    const int64_t corner = uni64(gm.cell) - (int64_t)h * a.nx - h;
-    const int64_t pstride = a.pol_stride * (int64_t)(2 * sizeof(T));
-    // one scalar base per pol (its byte offset made opaque, so that a lane's
-    // offset is added to it rather than folded into 64-bit vector arithmetic)
-    const char *gbp[NPOL];
-    for (int p = 0; p < NPOL; ++p)
-        gbp[p] = (const char *)a.grid + uni64(corner * (int64_t)(2 * sizeof(T)) + p * pstride);
-    const int row = a.nx * (int)(2 * sizeof(T));          // bytes per grid row
-    // lane's first tap and the per-step advance of 64 taps
-    const int dty = 64 / S, dtx = 64 - dty * S;
-    int ty = lane / S, tx = lane - (lane / S) * S;
-    int goff = ty * row + tx * (int)(2 * sizeof(T));
-    cpx<T> sum[NPOL];
-    for (int p = 0; p < NPOL; ++p) sum[p] = {(T)0, (T)0};
-    for (int t0 = 0; t0 < SS; t0 += 64 * NT) {
-        Raw cr[NT];
-        cpx<T> gv[NT][NPOL];
-        bool ok[NT];
-        int txs[NT], tys[NT];
-        for (int u = 0; u < NT; ++u) {
-            const int tap = t0 + u * 64 + lane;
-            ok[u] = tap < SS;
-            txs[u] = tx;
-            tys[u] = ty;
-            if (ok[u]) {
-                cr[u] = *(const Raw *)(cfb + (uint32_t)tap * (uint32_t)E);
-                for (int p = 0; p < NPOL; ++p) {
-                    const T *q = (const T *)(gbp[p] + (uint32_t)goff);
-                    gv[u][p] = {q[0], q[1]};
-                }
-            }
-            // advance by 64 taps
-            tx += dtx;
-            ty += dty;
-            goff += dty * row + dtx * (int)(2 * sizeof(T));
-            if (tx >= S) {
-                tx -= S;
-                ++ty;
-                goff += row - S * (int)(2 * sizeof(T));
-            }
-        }
-        for (int u = 0; u < NT; ++u) {
-            if (!ok[u]) continue;
-            if constexpr (RE) {
-                const T c = CFReal<ST>::decode(cr[u], sc);
-                for (int p = 0; p < NPOL; ++p) {
-                    sum[p].x = fma(c, gv[u][p].x, sum[p].x);
-                    sum[p].y = fma(c, gv[u][p].y, sum[p].y);
-                }
-            } else {
-                cpx<T> cv = CFRaw<ST>::decode(cr[u], sc);
-                if (cj) cv.y = -cv.y;
-                if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
-                for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
-            }
-        }
-        __builtin_amdgcn_s_waitcnt(kWaitVm0);
-    }
-    cpx<T> *out = (cpx<T> *)a.Vg;
-    for (int p = 0; p < NPOL; ++p) {
-        T x = wave_sum(sum[p].x), y = wave_sum(sum[p].y);
-        if (lane == 0) out[g * NPOL + p] = {x, y};
-    }
-}
-
-// Small supports (S <= 2 kDegridSmallH + 1): a 7 x 7 footprint would leave
-// most of a wavefront idle, so 16 lanes take one group (four groups per
-// wavefront), four taps per lane in flight, and reduce over their 16 lanes.
-constexpr int kDegridSmallH = 7;
-
-template <typename T, int ST, int NPOL, bool PO, bool RE>
-__global__ __launch_bounds__(256) void k_degrid_small(DegridArgs a) {
-    constexpr int E = CFRaw<ST>::bytes;
-    typedef typename std::conditional<RE, typename CFReal<ST>::R, typename CFRaw<ST>::R>::type Raw;
-    const int sub = threadIdx.x & 15;
-    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 4) + (threadIdx.x >> 4);
-    const bool live = g < a.n_groups;
-    cpx<T> sum[NPOL];
-    for (int p = 0; p < NPOL; ++p) sum[p] = {(T)0, (T)0};
-    if (live) {
-        const GroupMeta gm = a.groups[g];
-        const int h = gm.h;
-        const int S = 2 * h + 1;
-        const int SS = S * S;
-        const float invS = 1.0f / (float)S;
-        const char *cfb = (const char *)a.cf.table + gm.cf_off * E;
-        const int64_t corner = gm.cell - (int64_t)h * a.nx - h;
-        const T *grid = (const T *)a.grid;
-        for (int t0 = 0; t0 < SS; t0 += 64) {
-            Raw cr[4];
-            cpx<T> gv[4][NPOL];
-            int tys[4], txs[4];
-            for (int u = 0; u < 4; ++u) {
-                const int tap = t0 + u * 16 + sub;
-                int ty, tx;
-                divmod_small(tap, S, invS, ty, tx);
-                tys[u] = ty;
-                txs[u] = tx;
-                if (tap < SS) {
-                    cr[u] = *(const Raw *)(cfb + (int64_t)tap * E);
-                    const int64_t cell = corner + (int64_t)ty * a.nx + tx;
-                    for (int p = 0; p < NPOL; ++p) {
-                        const T *q = grid + 2 * (cell + p * a.pol_stride);
-                        gv[u][p] = {q[0], q[1]};
-                    }
-                }
-            }
-            for (int u = 0; u < 4; ++u) {
-                if (t0 + u * 16 + sub >= SS) continue;
-                if constexpr (RE) {
-                    const T c = CFReal<ST>::decode(cr[u], gm.sc);
-                    for (int p = 0; p < NPOL; ++p) {
-                        sum[p].x = fma(c, gv[u][p].x, sum[p].x);
-                        sum[p].y = fma(c, gv[u][p].y, sum[p].y);
-                    }
-                } else {
-                    cpx<T> cv = CFRaw<ST>::decode(cr[u], gm.sc);
-                    if (gm.conj) cv.y = -cv.y;
-                    if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
-                    for (int p = 0; p < NPOL; ++p) cmac_conj(sum[p], cv, gv[u][p]);
-                }
-            }
-        }
-    }
-    for (int p = 0; p < NPOL; ++p)
-        for (int off = 8; off > 0; off >>= 1) {
-            sum[p].x += __shfl_xor(sum[p].x, off);
-            sum[p].y += __shfl_xor(sum[p].y, off);
-        }
-    if (live && sub == 0) {
-        cpx<T> *out = (cpx<T> *)a.Vg;
-        for (int p = 0; p < NPOL; ++p) out[g * NPOL + p] = sum[p];
     }
 }
 
@@ -1587,7 +806,6 @@ __global__ __launch_bounds__(256) void k_sumwt_finish(int32_t nchan, const ChanC
 }
 
 // ---------------------------------------------------------------------------
-static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 template <typename T, int NPOL>
 static hipError_t presum_t(const lr_plan *P, const VisArgs &v, void *A, double *sumwt,
@@ -1686,70 +904,11 @@ static hipError_t grid_np(const TileArgs &ta, int64_t n_blocks, int npol, bool p
     }
 }
 
-template <typename T, int ST, int NPOL>
-static hipError_t grid_sep_t(const SepArgs &sa, int64_t n_blocks, int S, hipStream_t s) {
-    dim3 grd((unsigned)n_blocks), blk(kSepThreads);
-    const size_t lds = 2 * sizeof(T) * (size_t)(sa.O + 1) * S;
-    const int nt = (S * S + 63) / 64;
-    if (nt <= 1) hipLaunchKernelGGL((k_grid_sep<T, ST, NPOL, 1>), grd, blk, lds, s, sa);
-    else if (nt == 2) hipLaunchKernelGGL((k_grid_sep<T, ST, NPOL, 2>), grd, blk, lds, s, sa);
-    else if (nt == 3) hipLaunchKernelGGL((k_grid_sep<T, ST, NPOL, 3>), grd, blk, lds, s, sa);
-    else hipLaunchKernelGGL((k_grid_sep<T, ST, NPOL, 4>), grd, blk, lds, s, sa);
-    return hipGetLastError();
-}
-
-template <typename T, int ST>
-static hipError_t grid_sep_np(const SepArgs &sa, int64_t n_blocks, int npol, int S,
-                              hipStream_t s) {
-    switch (npol) {
-        case 1: return grid_sep_t<T, ST, 1>(sa, n_blocks, S, s);
-        case 2: return grid_sep_t<T, ST, 2>(sa, n_blocks, S, s);
-        default: return grid_sep_t<T, ST, 4>(sa, n_blocks, S, s);
-    }
-}
-
-bool sep_gridder(const lr_plan *P, const CFView &cf, int32_t mode, bool det) {
-    if (mode == GRID_PSF || det || P->po || !cf.real || cf.n_w != 1) return false;
-    static const int forced = [] {
-        const char *e = getenv("LR_GRIDDER");
-        if (!e) return 0;
-        if (!strcmp(e, "sep")) return 1;
-        if (!strcmp(e, "tile")) return -1;
-        return 0;
-    }();
-    if (forced < 0) return false;
-    // a real table with one w-plane and one frequency group: a single plane,
-    // and a tile's pairs sorted by pixel row alone (the sort key puts the
-    // frequency group ahead of the pixel)
-    return cf.n_fg == 1 && cf.h0 <= 7;
-}
-
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
                        int precision, int32_t npol, int32_t nx, int32_t ny, int32_t mode,
                        bool det, hipStream_t s) {
     const bool set = mode == GRID_SET;
-    if (sep_gridder(P, cf, mode, det)) {
-        const int64_t n_blocks = P->n_sep_parts + (set ? P->n_tiles : 0);
-        if (n_blocks == 0) return hipSuccess;
-        SepArgs sa{P->tp_group, P->tile_tp, P->sep_part, (int32_t)P->n_sep_parts, P->geo, A, grid,
-                   nullptr, cf.scale, cf.O, cf.h0, nx, ny, (nx + kTile - 1) / kTile,
-                   (ny + kTile - 1) / kTile, (int64_t)nx * ny, set ? 1 : 0};
-        const int S = 2 * cf.h0 + 1;
-        switch (precision) {
-            case LR_F64:
-                sa.table = (const char *)cf.table + cf.off0 * 16;
-                return grid_sep_np<double, LR_F64>(sa, n_blocks, npol, S, s);
-            case LR_F32:
-                sa.table = (const char *)cf.table + cf.off0 * 8;
-                return grid_sep_np<float, LR_F32>(sa, n_blocks, npol, S, s);
-            case LR_F32_CF16:
-                sa.table = (const char *)cf.table + cf.off0 * 4;
-                return grid_sep_np<float, LR_F32_CF16>(sa, n_blocks, npol, S, s);
-            default:
-                sa.table = (const char *)cf.table + cf.off0 * 4;
-                return grid_sep_np<float, LR_F32_CFBF16>(sa, n_blocks, npol, S, s);
-        }
-    }
+    if (sep_gridder(P, cf, mode, det)) return launch_grid_sep(P, cf, A, grid, precision, npol, nx, ny, set, s);
     // GRID_SET: one more workgroup per tile clears the tiles without pairs
     const int64_t nc = P->n_chunks + (set ? P->n_tiles : 0);
     if (nc == 0) return hipSuccess;
@@ -1809,49 +968,6 @@ hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *
         case 1: return f64 ? setup_t<double, 1>(sa, n_blocks, s) : setup_t<float, 1>(sa, n_blocks, s);
         case 2: return f64 ? setup_t<double, 2>(sa, n_blocks, s) : setup_t<float, 2>(sa, n_blocks, s);
         default: return f64 ? setup_t<double, 4>(sa, n_blocks, s) : setup_t<float, 4>(sa, n_blocks, s);
-    }
-}
-
-template <typename T, int ST, int NPOL>
-static hipError_t degrid_t(const DegridArgs &da, bool po, bool small, hipStream_t s) {
-    dim3 blk(256);
-    const bool re = !po && da.cf.real;
-    if (small) {
-        dim3 grd(nblk(da.n_groups, 16));
-        if (po) hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, true, false>), grd, blk, 0, s, da);
-        else if (re) hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, false, true>), grd, blk, 0, s, da);
-        else hipLaunchKernelGGL((k_degrid_small<T, ST, NPOL, false, false>), grd, blk, 0, s, da);
-        return hipGetLastError();
-    }
-    dim3 grd(nblk(da.n_groups, 4));
-    if (po) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, true, false>), grd, blk, 0, s, da);
-    else if (re) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false, true>), grd, blk, 0, s, da);
-    else hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false, false>), grd, blk, 0, s, da);
-    return hipGetLastError();
-}
-
-template <typename T, int ST>
-static hipError_t degrid_np(const DegridArgs &da, int npol, bool po, bool small,
-                            hipStream_t s) {
-    switch (npol) {
-        case 1: return degrid_t<T, ST, 1>(da, po, small, s);
-        case 2: return degrid_t<T, ST, 2>(da, po, small, s);
-        default: return degrid_t<T, ST, 4>(da, po, small, s);
-    }
-}
-
-hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
-                         int precision, int32_t npol, int32_t nx, int32_t ny, int32_t h_max,
-                         hipStream_t s) {
-    if (P->n_groups == 0) return hipSuccess;
-    DegridArgs da{P->groups, P->n_groups, grid, Vg, cf, nx, ny, (int64_t)nx * ny};
-    bool po = P->po != 0;
-    bool sm = h_max <= kDegridSmallH;
-    switch (precision) {
-        case LR_F64: return degrid_np<double, LR_F64>(da, npol, po, sm, s);
-        case LR_F32: return degrid_np<float, LR_F32>(da, npol, po, sm, s);
-        case LR_F32_CF16: return degrid_np<float, LR_F32_CF16>(da, npol, po, sm, s);
-        default: return degrid_np<float, LR_F32_CFBF16>(da, npol, po, sm, s);
     }
 }
 

@@ -331,6 +331,19 @@ __global__ __launch_bounds__(256) void k_chunk_cost(const int32_t *chunk_start,
     }
 }
 
+// Table plane of each chunk (that of its first pair; a tile's pairs follow
+// the group order, whose keys put the frequency group and w-plane first, so
+// a chunk rarely spans two planes); the chunk ids ride along.
+__global__ void k_chunk_plane(const int32_t *chunk_start, const int32_t *tp_group,
+                              const GroupMeta *groups, int32_t n_w, int64_t n_chunks,
+                              uint32_t *key, int32_t *id) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n_chunks) return;
+    const GroupMeta &g = groups[tp_group[chunk_start[c]]];
+    key[c] = (uint32_t)(g.fg * n_w + g.k);
+    id[c] = (int32_t)c;
+}
+
 __global__ void k_chunk_end(int32_t *chunk_start, int64_t n_chunks, int64_t n) {
     if (threadIdx.x == 0) chunk_start[n_chunks] = (int32_t)n;
 }
@@ -674,13 +687,24 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
                        ntp, P->n_tiles, P->tile_tp);
     // with a kernel table the last-level cache holds, the gridder launches
     // chunks largest first (a stable sort: ties keep tile order), so the
-    // long ones do not trail the launch; a larger table keeps tile order,
-    // whose neighbouring chunks share kernel planes in the cache
-    if (lpt && nch > 0) {
-        hipLaunchKernelGGL(k_chunk_cost, dim3(blocks(nch * 64, 256)), dim3(256), 0, s,
-                           P->chunk_start, vals_a, nch, tk_a, flags);
+    // long ones do not trail the launch; with a larger table it launches
+    // them plane by plane (tile order within a plane), so the chunks in
+    // flight read one plane of the table, which the cache holds, instead
+    // of all of them
+    if (nch > 0) {
+        int end_bits = 32;
+        if (lpt) {
+            hipLaunchKernelGGL(k_chunk_cost, dim3(blocks(nch * 64, 256)), dim3(256), 0, s,
+                               P->chunk_start, vals_a, nch, tk_a, flags);
+        } else {
+            hipLaunchKernelGGL(k_chunk_plane, dim3(blocks(nch, 256)), dim3(256), 0, s,
+                               P->chunk_start, P->tp_group, P->groups, cf.n_w, nch, tk_a, flags);
+            end_bits = 1;
+            while (end_bits < 32 && ((int64_t)1 << end_bits) < (int64_t)cf.n_fg * cf.n_w)
+                ++end_bits;
+        }
         e = rocprim::radix_sort_pairs(temp, temp_bytes, tk_a, (uint32_t *)scan, flags,
-                                      P->chunk_order, (size_t)nch, 0, 32, s);
+                                      P->chunk_order, (size_t)nch, 0, end_bits, s);
         if (e != hipSuccess) return e;
     } else {
         P->chunk_order = nullptr;

@@ -74,6 +74,10 @@ hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *
 // workgroup per tile, every cell written once): then GRID_SET needs no
 // clearing of shared tiles beforehand.
 bool sep_gridder(const lr_plan *P, const CFView &cf, int32_t mode, bool det);
+// The separable gridder's launch (k_sep.hip), when sep_gridder() chose it.
+hipError_t launch_grid_sep(const lr_plan *P, const CFView &cf, const void *A, void *grid,
+                           int precision, int32_t npol, int32_t nx, int32_t ny, bool set,
+                           hipStream_t s);
 // Set-up of a gridding call, one launch: zero the group sums A (a_bytes)
 // and, when given, sumwt and counters; under GRID_SET also the tiles that
 // several chunks share (they are then added to atomically).
