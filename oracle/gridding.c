@@ -13,6 +13,11 @@
  *   map      (row, chan) -> pixel p, oversampling offset o, w-plane k, conj flag
  *   grid     grid[P][pol][p_v + t_v][p_u + t_u] += Ct(o, t) * phi(t) * W * V
  *   degrid   V = sum_t conj(Ct(o, t) * phi(t)) * grid[P][pol][p_v + t_v][p_u + t_u]
+ *
+ * With a sparse Mueller matrix of CFs (the table holds several kinds, and
+ * mueller[q * npol + p] is the kind of element M[q][p], -1 for none), the
+ * pols mix: grid pol p receives sum_q Ct_qp W_q V_q, and V_q = sum_p
+ * conj(Ct_qp) grid_p.  Without one, M is the identity times the one table.
  *   sumwt    sum of W over kept samples, per (plane, pol)
  *   psf      1/2 (g + H g), g = unit-visibility weight grid, (H g)[i][j] =
  *            conj g[ny - i][nx - j]
@@ -50,6 +55,8 @@ typedef struct {
     const double *ant_dlm;            /* [nant][2] radians */
     const double *f_scale;            /* [nchan]: pi * D * nu / c */
     double du_dl, dv_dm;              /* uv cell size times... see phasor() */
+    const int32_t *mueller;           /* [npol][npol] kind of M[q][p], -1 none; NULL: diagonal */
+    int64_t kind_stride;              /* complex elements per kind */
 } octx;
 
 typedef struct {
@@ -138,13 +145,20 @@ static int phasor(const octx *c, int64_t r, int32_t ch, const omap *m, double *f
     return 1;
 }
 
-/* Pointer to table entry C[fg][k][ov + O/2][ou + O/2][0][0] */
-static const double *cf_sub(const octx *c, const omap *m) {
+/* Pointer to table entry C[kind][fg][k][ov + O/2][ou + O/2][0][0] */
+static const double *cf_sub(const octx *c, const omap *m, int32_t kind) {
     int32_t S = 2 * c->h[m->k] + 1;
     int64_t no = c->O + 1;
-    int64_t idx = c->plane_off[(int64_t)m->fg * c->n_w + m->k] +
+    int64_t idx = (int64_t)kind * c->kind_stride +
+                  c->plane_off[(int64_t)m->fg * c->n_w + m->k] +
                   (((int64_t)(m->ov + c->O / 2) * no + (m->ou + c->O / 2)) * S * S);
     return c->cf + 2 * idx;
+}
+
+/* Kind of Mueller element M[q][p] (-1: none) */
+static int32_t kind_of(const octx *c, int32_t q, int32_t p) {
+    if (c->mueller) return c->mueller[q * c->npol + p];
+    return q == p ? 0 : -1;
 }
 
 void oracle_map(const octx *c, int32_t *out) {
@@ -206,10 +220,13 @@ void oracle_grid(const octx *c, const double *vis, const double *weight, double 
                 if (m.pv + h < y0 || m.pv - h >= y1) continue;
                 double f = 1.0;
                 int po = phasor(c, r, ch, &m, &f, phur, phui, phvr, phvi);
-                const double *C = cf_sub(c, &m);
                 double csign = m.conj ? -1.0 : 1.0;
-                for (int32_t p = 0; p < c->npol; ++p) {
-                    int64_t s = (r * c->nchan + ch) * c->npol + p;
+                for (int32_t p = 0; p < c->npol; ++p)
+                for (int32_t q = 0; q < c->npol; ++q) {
+                    int32_t kind = kind_of(c, q, p);
+                    if (kind < 0) continue;
+                    const double *C = cf_sub(c, &m, kind);
+                    int64_t s = (r * c->nchan + ch) * c->npol + q;
                     double W = weight[s];
                     if (W == 0.0) continue;
                     double ar, ai;
@@ -267,17 +284,20 @@ void oracle_degrid(const octx *c, const double *grid, const double *weight, doub
                 double f = 1.0;
                 int po = 0;
                 if (m.keep) po = phasor(c, r, ch, &m, &f, phur, phui, phvr, phvi);
-                for (int32_t p = 0; p < c->npol; ++p) {
-                    int64_t s = (r * c->nchan + ch) * c->npol + p;
+                for (int32_t q = 0; q < c->npol; ++q) {
+                    int64_t s = (r * c->nchan + ch) * c->npol + q;
                     vis[2 * s] = 0.0;
                     vis[2 * s + 1] = 0.0;
                     if (!m.keep) continue;
                     if (weight && weight[s] == 0.0) continue;
                     int32_t h = c->h[m.k], S = 2 * h + 1;
-                    const double *C = cf_sub(c, &m);
                     double csign = m.conj ? -1.0 : 1.0;
-                    const double *g = grid + 2 * (((int64_t)P * c->npol + p) * plane);
                     double sr = 0.0, si = 0.0;
+                    for (int32_t p = 0; p < c->npol; ++p) {
+                    int32_t kind = kind_of(c, q, p);
+                    if (kind < 0) continue;
+                    const double *C = cf_sub(c, &m, kind);
+                    const double *g = grid + 2 * (((int64_t)P * c->npol + p) * plane);
                     for (int32_t tv = -h; tv <= h; ++tv)
                         for (int32_t tu = -h; tu <= h; ++tu) {
                             int64_t ti = (int64_t)(tv + h) * S + (tu + h);
@@ -295,6 +315,7 @@ void oracle_degrid(const octx *c, const double *grid, const double *weight, doub
                             sr += cr * gr + ci * gim;
                             si += cr * gim - ci * gr;
                         }
+                    }
                     vis[2 * s] = sr;
                     vis[2 * s + 1] = si;
                 }
@@ -344,7 +365,7 @@ void oracle_psf_mirror(const octx *c, const double *weight, double *grid) {
             int32_t h = c->h[m.k], S = 2 * h + 1;
             double f = 1.0;
             int po = phasor(c, r, ch, &m, &f, phur, phui, phvr, phvi);
-            const double *C = cf_sub(c, &m);
+            const double *C = cf_sub(c, &m, 0);
             double csign = m.conj ? -1.0 : 1.0;
             for (int32_t p = 0; p < c->npol; ++p) {
                 int64_t s = (r * c->nchan + ch) * c->npol + p;

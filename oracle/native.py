@@ -42,6 +42,7 @@ class OCtx(C.Structure):
         ("chan_plane", C.c_void_p), ("chan_fg", C.c_void_p),
         ("ant1", C.c_void_p), ("ant2", C.c_void_p), ("ant_dlm", C.c_void_p),
         ("f_scale", C.c_void_p), ("du_dl", C.c_double), ("dv_dm", C.c_double),
+        ("mueller", C.c_void_p), ("kind_stride", C.c_int64),
     ]
 
 
@@ -106,6 +107,13 @@ class Problem:
         c.f_scale = _p(self.f_scale)
         c.du_dl = 1.0 / (nx * cell_l)
         c.dv_dm = 1.0 / (ny * cell_m)
+        self.mueller = None
+        if getattr(ocf, "mueller", None) is not None:
+            if npol != 4:
+                raise ValueError("a Mueller table needs the four correlations")
+            self.mueller = np.ascontiguousarray(ocf.mueller, np.int32).ravel()
+        c.mueller = _p(self.mueller)
+        c.kind_stride = int(getattr(ocf, "kind_elems", 0))
         self.ctx = c
         self.cell_l, self.cell_m = cell_l, cell_m
         self.nrow, self.nchan = c.nrow, c.nchan

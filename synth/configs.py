@@ -40,6 +40,10 @@ class CFSetup:
     fg_hz: np.ndarray    # [n_fg] A-term frequency of each group
     dish_m: float = 25.0
     screen_m: int = 0    # 0 = smallest even >= 2 * max support
+    pol_beam: int = 0    # 0: one power pattern for every pol; 1..3: polarised
+                         # beam, Mueller terms up to order pol_beam - 1 in leakage
+    beam_ellipticity: float = 0.0
+    beam_leakage: float = 0.0
 
     @property
     def n_fg(self):
