@@ -108,6 +108,24 @@ typedef struct {
     double dish_m;         /* Airy dish diameter (A term) */
     int32_t screen_m;      /* M, even; 0 = smallest even >= 2 S_max */
     lr_precision storage;  /* element type of the table */
+    /* Sparse Mueller matrix of CFs (the AWP framework's VisResampler holds
+     * F M^DD as a 2-D sparse matrix of kernels; M^DD = J (x) J for identical
+     * antennas, Eq. ME).  pol_beam = 0: one scalar A term, the Airy power
+     * pattern, for every correlation (a diagonal Mueller matrix of one
+     * kernel).  pol_beam = 1, 2, 3: a polarised beam for linear feeds
+     * (correlations XX, XY, YX, YY, index q = 2 q1 + q2), J = [[E_X, d],
+     * [d, E_Y]] with a(x) = 2 J1(x)/x and s = pi dish_m nu_fg / c:
+     *   E_X = a(s sqrt((l/(1+eta))^2 + (m/(1-eta))^2)), E_Y: eta -> -eta,
+     *   d   = kappa (s l)(s m) a(s rho)   (four-lobed cross-polar leakage),
+     * keeping the elements M[q][p] = J[q1][p1] J[q2][p2] of order below
+     * pol_beam in d (4, 12 or all 16 elements).  The table then holds the
+     * distinct products ("kinds") one after the other: E_X^2, E_Y^2,
+     * E_X E_Y, E_X d, E_Y d, d^2 (3, 5 or 6 of them).  Needs LR_TERM_A and
+     * npol = 4.  The model is this library's reading: the paper gives no
+     * polarised beam.  Zero-initialised fields keep the scalar beam. */
+    int32_t pol_beam;          /* 0 .. 3 */
+    double beam_ellipticity;   /* eta, |eta| < 0.5 */
+    double beam_leakage;       /* kappa, |kappa| <= 10 */
 } lr_cf_spec;
 
 typedef struct lr_cf lr_cf;       /* host handle over a caller-owned device blob */
@@ -163,16 +181,25 @@ lr_status lr_cf_attach(const lr_cf_spec *spec, const lr_grid_spec *grid, void *c
 void lr_cf_free(lr_cf *cf);
 
 /* Per-plane storage exponent e_k (table entries are C * 2^e_k) read back to
- * the host into exps[n_fg * n_w]; synchronises the stream. */
+ * the host into exps[n_kind * n_fg * n_w] (kind-major); synchronises the
+ * stream. */
 lr_status lr_cf_scale_exponents(const lr_cf *cf, int32_t *exps, lr_stream stream);
 
 /* Where the table lives in the blob: byte offset of element 0, bytes per
- * complex element (16 f64, 8 f32, 4 fp16/bf16 pair), element count, and the
- * element offset of every plane (fg, k) in plane_off[n_fg * n_w] (may be
- * NULL).  The table is laid out [fg][k][o_v + O/2][o_u + O/2][t_v + h_k]
- * [t_u + h_k], o in [-O/2, O/2]. */
+ * complex element (16 f64, 8 f32, 4 fp16/bf16 pair), element count (of
+ * every kind), and the element offset of every plane (fg, k) of kind 0 in
+ * plane_off[n_fg * n_w] (may be NULL).  The table is laid out [kind][fg][k]
+ * [o_v + O/2][o_u + O/2][t_v + h_k][t_u + h_k], o in [-O/2, O/2]; kind
+ * kappa starts kappa * n_elems / n_kind elements after kind 0. */
 lr_status lr_cf_layout(const lr_cf *cf, size_t *table_offset, size_t *elem_bytes,
                        int64_t *n_elems, int64_t *plane_off);
+
+/* The Mueller kinds of the table: *n_kind (1 for the scalar beam) and, when
+ * kind_of is not NULL, kind_of[q * 4 + p] = kind of element M[q][p] or -1
+ * (scalar beam: 0 on the diagonal of npol x npol, -1 elsewhere, 16 entries
+ * written).  Gridding adds sum_q Ct_qp W_q V_q into pol p; degridding gives
+ * V_q = sum_p conj(Ct_qp) grid_p.  Host only. */
+lr_status lr_cf_kinds(const lr_cf *cf, int32_t *n_kind, int32_t *kind_of);
 
 /* ---- binning (PreSolvePrep) ------------------------------------------------ */
 
@@ -247,6 +274,9 @@ lr_status lr_set_profile_events(void *start, void *stop);
 /* Gridding G (Eq. IMAGE-MOD): grid[P][pol][p_v + t_v][p_u + t_u] +=
  * Ct(o, t) phi(t) W V for every kept sample, Ct = C or conj C (w < 0),
  * phi = pointing phasor (Eq. CIJ) when ant ids and offsets are given.
+ * With a Mueller table (pol_beam > 0) grid pol p receives sum_q Ct_qp
+ * W_q V_q over the correlations q its column of the sparse matrix holds
+ * (one gridder pass per kind; the time grows with the kinds).
  * sumwt [nplane][npol] (FP64) += W over kept samples; counters += class
  * counts.  sumwt and counters may be NULL. */
 lr_status lr_grid(const lr_cf *cf, const lr_vis *vis, lr_precision precision, void *grid,
@@ -281,13 +311,16 @@ lr_status lr_grid_static(const lr_cf *cf, const lr_vis *vis, lr_precision precis
 
 /* Degridding D (Eq. ME-MOD-GRIDDED): vis = sum_t conj(Ct(o, t) phi(t)) grid[...]
  * for kept samples; flagged and dropped samples are written as 0.  No
- * weights enter the sum.  counters may be NULL. */
+ * weights enter the sum.  counters may be NULL.  With a Mueller table
+ * (pol_beam > 0) correlation q sums conj(Ct_qp) over the grid pols p its
+ * row of the sparse matrix holds (one pass per kind). */
 lr_status lr_degrid(const lr_cf *cf, lr_vis *vis, lr_precision precision, const void *grid,
                     int64_t *counters, void *work, size_t work_bytes, lr_stream stream);
 
 /* PSF: psf_grid += 1/2 (g + H g), g = the gridding of unit visibilities with
  * weights W under the PSF footprint rule, (H g)[i][j] = conj g[ny-i][nx-j].
- * The result is Hermitian, so its image is real.  vis->vis is not read. */
+ * The result is Hermitian, so its image is real.  vis->vis is not read.
+ * Tables of one scalar beam only (LR_E_CF for pol_beam > 0). */
 lr_status lr_make_psf(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
                       void *psf_grid, double *sumwt, int64_t *counters, void *work,
                       size_t work_bytes, lr_stream stream);
@@ -335,7 +368,8 @@ lr_status lr_ps_taper(const lr_cf *cf, int32_t n, void *out, lr_stream stream);
  * (iy - ny/2) cell_m); 1 everywhere without an A term, 0 where the weights
  * sum to 0.  fg_weight: device float64 [nplane][npol][n_fg], the sums of
  * weights of each frequency group's channels (lr_sumwt on those channels);
- * out: device float64 [nplane][npol][ny][nx]. */
+ * out: device float64 [nplane][npol][ny][nx].  Tables of a scalar beam only
+ * (LR_E_CF for pol_beam > 0: a polarised beam mixes the pols). */
 lr_status lr_pb_image(const lr_cf *cf, const double *fg_weight, void *out, lr_stream stream);
 
 /* lr_image_normalize with the weight image: out = Re(img) / (gcf_x[ix]

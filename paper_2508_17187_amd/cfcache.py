@@ -69,6 +69,10 @@ def describe(grid, spec):
     g = {f: _exact(get(f)) for f in _GRID_FIELDS}
     s = {f: _exact(spec[f]) for f in _SPEC_FIELDS}
     s["fg_hz"] = [float(x).hex() for x in np.asarray(spec["fg_hz"], np.float64).ravel()]
+    if spec.get("pol_beam", 0):
+        # a polarised beam (scalar-beam tables keep the names they had)
+        for f in ("pol_beam", "beam_ellipticity", "beam_leakage"):
+            s[f] = _exact(spec[f])
     return {"grid": g, "spec": s}
 
 

@@ -121,6 +121,31 @@ __device__ __forceinline__ double airy_pow(double x) {
     return b * b;
 }
 
+__device__ __forceinline__ double airy_volt(double x) {
+    return x == 0.0 ? 1.0 : 2.0 * j1(x) / x;
+}
+
+// Mueller kind `kind` of the polarised beam at (l, m): the product of two
+// elements of J = [[E_X, d], [d, E_Y]] (kinds E_X^2, E_Y^2, E_X E_Y, E_X d,
+// E_Y d, d^2), with elliptical Airy voltage patterns and the four-lobed
+// leakage d = kappa (s l)(s m) a(s rho), s = pi D nu / c.
+__device__ double pol_beam_kind(int kind, double l, double m, double s, double eta,
+                                double kappa) {
+    const double lx = l / (1.0 + eta), mx = m / (1.0 - eta);
+    const double ly = l / (1.0 - eta), my = m / (1.0 + eta);
+    const double ex = airy_volt(s * sqrt(lx * lx + mx * mx));
+    const double ey = airy_volt(s * sqrt(ly * ly + my * my));
+    const double d = kappa * (s * l) * (s * m) * airy_volt(s * sqrt(l * l + m * m));
+    switch (kind) {
+        case 0: return ex * ex;
+        case 1: return ey * ey;
+        case 2: return ex * ey;
+        case 3: return ex * d;
+        case 4: return ey * d;
+        default: return d * d;
+    }
+}
+
 __global__ void k_screen(CFBuildArgs a, const double *T, double w_k, double nu_fg, double2 *scr) {
     int n1 = a.M + 1;
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -132,8 +157,13 @@ __global__ void k_screen(CFBuildArgs a, const double *T, double w_k, double nu_f
     double wgt = ((j == 0 || j == a.M) ? 0.5 : 1.0) * ((i == 0 || i == a.M) ? 0.5 : 1.0);
     double re = wgt * T[i] * T[j], im = 0.0;
     if (a.terms & LR_TERM_A) {
-        double rho = sqrt(l * l + m * m);
-        re *= airy_pow(((M_PI * a.dish_m) * nu_fg) * rho / kCLight);
+        if (a.pol_beam) {
+            re *= pol_beam_kind(a.kind, l, m, ((M_PI * a.dish_m) * nu_fg) / kCLight, a.eta,
+                                a.kappa);
+        } else {
+            double rho = sqrt(l * l + m * m);
+            re *= airy_pow(((M_PI * a.dish_m) * nu_fg) * rho / kCLight);
+        }
     }
     if (a.terms & LR_TERM_W) {
         double r2 = l * l + m * m;
@@ -378,7 +408,8 @@ hipError_t launch_pb_image(const lr_cf *cf, const double *w, double *out, hipStr
     return hipGetLastError();
 }
 
-hipError_t launch_cf_build(const lr_cf *cf, const CFBuildArgs &a, void *work, hipStream_t s) {
+hipError_t launch_cf_build(const lr_cf *cf, const CFBuildArgs &a0, void *work, hipStream_t s) {
+    CFBuildArgs a = a0;
     auto al = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const lr_cf_spec &sp = cf->spec;
     int M = a.M, O = a.O;
@@ -403,41 +434,47 @@ hipError_t launch_cf_build(const lr_cf *cf, const CFBuildArgs &a, void *work, hi
     int n_planes = sp.n_fg * sp.n_w;
     int st = sp.storage;
     if (st == LR_F64 || st == LR_F32)
-        hipLaunchKernelGGL(k_unit_scale, dim3(nblk(n_planes, 256)), dim3(256), 0, s,
-                           cf->d_exp, cf->d_scale, n_planes);
+        hipLaunchKernelGGL(k_unit_scale, dim3(nblk(n_planes * cf->n_kind, 256)), dim3(256), 0,
+                           s, cf->d_exp, cf->d_scale, n_planes * cf->n_kind);
     double norm = (double)M * (double)M;
-    for (int g = 0; g < sp.n_fg; ++g) {
-        for (int k = 0; k < sp.n_w; ++k) {
-            double w_k = sp.n_w > 1 ? ((double)k * sp.w_max) / (double)(sp.n_w - 1) : 0.0;
-            int h = cf->h[k];
-            int S = 2 * h + 1;
-            int NU = O * S + 1;
-            int n0 = O / 2 + O * h;
-            hipLaunchKernelGGL(k_screen, dim3(nblk((int64_t)(M + 1) * (M + 1), 256)),
-                               dim3(256), 0, s, a, T, w_k, cf->fg_hz[g], scr);
-            hipLaunchKernelGGL(k_dft_rows, dim3(nblk((int64_t)(M + 1) * NU, 256)), dim3(256),
-                               0, s, scr, tw, M, N, NU, n0, A);
-            int pi = g * sp.n_w + k;
-            int64_t n_ent = (int64_t)(O + 1) * (O + 1) * S * S;
-            char *dst = (char *)cf->d_table + cf->plane_off[pi] * cf->elem_bytes;
-            if (st == LR_F64) {
-                hipLaunchKernelGGL(k_dft_cols<0>, dim3(nblk(n_ent, 256)), dim3(256), 0, s, A,
-                                   tw, M, N, NU, O, h, norm, (void *)dst, maxbits);
-            } else if (st == LR_F32) {
-                hipLaunchKernelGGL(k_dft_cols<1>, dim3(nblk(n_ent, 256)), dim3(256), 0, s, A,
-                                   tw, M, N, NU, O, h, norm, (void *)dst, maxbits);
-            } else {
-                hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, maxbits);
-                hipLaunchKernelGGL(k_dft_cols<2>, dim3(nblk(n_ent, 256)), dim3(256), 0, s, A,
-                                   tw, M, N, NU, O, h, norm, (void *)plane, maxbits);
-                hipLaunchKernelGGL(k_plane_exp, dim3(1), dim3(64), 0, s, maxbits,
-                                   cf->d_exp + pi, cf->d_scale + pi);
-                if (st == LR_F32_CF16)
-                    hipLaunchKernelGGL(k_convert16<0>, dim3(nblk(n_ent, 256)), dim3(256), 0, s,
-                                       plane, n_ent, cf->d_exp + pi, (uint32_t *)dst);
-                else
-                    hipLaunchKernelGGL(k_convert16<1>, dim3(nblk(n_ent, 256)), dim3(256), 0, s,
-                                       plane, n_ent, cf->d_exp + pi, (uint32_t *)dst);
+    for (int kind = 0; kind < cf->n_kind; ++kind) {
+        a.kind = kind;
+        for (int g = 0; g < sp.n_fg; ++g) {
+            for (int k = 0; k < sp.n_w; ++k) {
+                double w_k = sp.n_w > 1 ? ((double)k * sp.w_max) / (double)(sp.n_w - 1) : 0.0;
+                int h = cf->h[k];
+                int S = 2 * h + 1;
+                int NU = O * S + 1;
+                int n0 = O / 2 + O * h;
+                hipLaunchKernelGGL(k_screen, dim3(nblk((int64_t)(M + 1) * (M + 1), 256)),
+                                   dim3(256), 0, s, a, T, w_k, cf->fg_hz[g], scr);
+                hipLaunchKernelGGL(k_dft_rows, dim3(nblk((int64_t)(M + 1) * NU, 256)), dim3(256),
+                                   0, s, scr, tw, M, N, NU, n0, A);
+                // plane index of the scale arrays (kind-major) and the plane's
+                // place in the table (each kind laid out as the scalar table)
+                int pi = kind * n_planes + g * sp.n_w + k;
+                int64_t n_ent = (int64_t)(O + 1) * (O + 1) * S * S;
+                char *dst = (char *)cf->d_table +
+                            (kind * cf->kind_elems + cf->plane_off[g * sp.n_w + k]) * cf->elem_bytes;
+                if (st == LR_F64) {
+                    hipLaunchKernelGGL(k_dft_cols<0>, dim3(nblk(n_ent, 256)), dim3(256), 0, s, A,
+                                       tw, M, N, NU, O, h, norm, (void *)dst, maxbits);
+                } else if (st == LR_F32) {
+                    hipLaunchKernelGGL(k_dft_cols<1>, dim3(nblk(n_ent, 256)), dim3(256), 0, s, A,
+                                       tw, M, N, NU, O, h, norm, (void *)dst, maxbits);
+                } else {
+                    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, maxbits);
+                    hipLaunchKernelGGL(k_dft_cols<2>, dim3(nblk(n_ent, 256)), dim3(256), 0, s, A,
+                                       tw, M, N, NU, O, h, norm, (void *)plane, maxbits);
+                    hipLaunchKernelGGL(k_plane_exp, dim3(1), dim3(64), 0, s, maxbits,
+                                       cf->d_exp + pi, cf->d_scale + pi);
+                    if (st == LR_F32_CF16)
+                        hipLaunchKernelGGL(k_convert16<0>, dim3(nblk(n_ent, 256)), dim3(256), 0, s,
+                                           plane, n_ent, cf->d_exp + pi, (uint32_t *)dst);
+                    else
+                        hipLaunchKernelGGL(k_convert16<1>, dim3(nblk(n_ent, 256)), dim3(256), 0, s,
+                                           plane, n_ent, cf->d_exp + pi, (uint32_t *)dst);
+                }
             }
         }
     }

@@ -14,7 +14,35 @@ struct DegridArgs {
     CFView cf;
     int32_t nx, ny;
     int64_t pol_stride;
+    uint32_t mix;     // Mueller pass: bit q * NPOL + p adds grid pol p's gather into q (0: none)
+    int32_t accum;    // add to Vg (later Mueller passes) instead of writing it
 };
+
+// A group's NPOL gathers written to Vg: as they are, or (a Mueller pass)
+// correlation q gets the sum of the pols p its mask bits select, added to
+// what earlier passes left when accum is set.
+template <typename T, int NPOL>
+__device__ __forceinline__ void store_group(const DegridArgs &a, int64_t g, const cpx<T> (&v)[NPOL]) {
+    cpx<T> *out = (cpx<T> *)a.Vg + g * NPOL;
+    for (int q = 0; q < NPOL; ++q) {
+        cpx<T> r;
+        if (a.mix == 0) {
+            r = v[q];
+        } else {
+            r = {(T)0, (T)0};
+            for (int p = 0; p < NPOL; ++p)
+                if ((a.mix >> (q * NPOL + p)) & 1u) {
+                    r.x += v[p].x;
+                    r.y += v[p].y;
+                }
+        }
+        if (a.accum) {
+            r.x += out[q].x;
+            r.y += out[q].y;
+        }
+        out[q] = r;
+    }
+}
 
 // Taps per lane whose loads are in flight together in the degridder: 4, or
 // 8 with 4-byte (FP16 / BF16) kernel values, whose raw words take half the
@@ -39,7 +67,7 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
     const int h = uni(gm.h);
     const int S = 2 * h + 1;
     const int SS = S * S;
-    const float sc = gm.sc;
+    const float sc = a.cf.scale[(int64_t)gm.fg * a.cf.n_w + gm.k];
     const bool cj = uni(gm.conj) != 0;
     const char *cfb = (const char *)a.cf.table + uni64(gm.cf_off) * E;
     // corner cell (tap (0, 0)) of pol 0
@@ -103,11 +131,9 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
             }
         }
     }
-    cpx<T> *out = (cpx<T> *)a.Vg;
-    for (int p = 0; p < NPOL; ++p) {
-        T x = wave_sum(sum[p].x), y = wave_sum(sum[p].y);
-        if (lane == 0) out[g * NPOL + p] = {x, y};
-    }
+    cpx<T> tot[NPOL];
+    for (int p = 0; p < NPOL; ++p) tot[p] = {wave_sum(sum[p].x), wave_sum(sum[p].y)};
+    if (lane == 0) store_group<T, NPOL>(a, g, tot);
 }
 
 // Small supports (S <= 2 kDegridSmallH + 1): a 7 x 7 footprint would leave
@@ -130,6 +156,7 @@ __global__ __launch_bounds__(256) void k_degrid_small(DegridArgs a) {
         const int S = 2 * h + 1;
         const int SS = S * S;
         const float invS = 1.0f / (float)S;
+        const float sc = a.cf.scale[(int64_t)gm.fg * a.cf.n_w + gm.k];
         const char *cfb = (const char *)a.cf.table + gm.cf_off * E;
         const int64_t corner = gm.cell - (int64_t)h * a.nx - h;
         const T *grid = (const T *)a.grid;
@@ -156,13 +183,13 @@ __global__ __launch_bounds__(256) void k_degrid_small(DegridArgs a) {
             for (int u = 0; u < 4; ++u) {
                 const bool in = t0 + u * 16 + sub < SS;
                 if constexpr (RE) {
-                    const T c = in ? CFReal<ST>::decode(cr[u], gm.sc) : (T)0;
+                    const T c = in ? CFReal<ST>::decode(cr[u], sc) : (T)0;
                     for (int p = 0; p < NPOL; ++p) {
                         sum[p].x = fma(c, gv[u][p].x, sum[p].x);
                         sum[p].y = fma(c, gv[u][p].y, sum[p].y);
                     }
                 } else {
-                    cpx<T> cv = CFRaw<ST>::decode(cr[u], gm.sc);
+                    cpx<T> cv = CFRaw<ST>::decode(cr[u], sc);
                     if (!in) cv = {(T)0, (T)0};
                     if (gm.conj) cv.y = -cv.y;
                     if (PO) cv = cmul(cv, phasor<T>(gm, txs[u] - h, tys[u] - h, a.cf.O));
@@ -176,10 +203,7 @@ __global__ __launch_bounds__(256) void k_degrid_small(DegridArgs a) {
             sum[p].x += __shfl_xor(sum[p].x, off);
             sum[p].y += __shfl_xor(sum[p].y, off);
         }
-    if (live && sub == 0) {
-        cpx<T> *out = (cpx<T> *)a.Vg;
-        for (int p = 0; p < NPOL; ++p) out[g * NPOL + p] = sum[p];
-    }
+    if (live && sub == 0) store_group<T, NPOL>(a, g, sum);
 }
 
 template <typename T, int ST, int NPOL>
@@ -212,9 +236,10 @@ static hipError_t degrid_np(const DegridArgs &da, int npol, bool po, bool small,
 
 hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
                          int precision, int32_t npol, int32_t nx, int32_t ny, int32_t h_max,
-                         hipStream_t s) {
+                         uint32_t mix, bool accum, hipStream_t s) {
     if (P->n_groups == 0) return hipSuccess;
-    DegridArgs da{P->groups, P->n_groups, grid, Vg, cf, nx, ny, (int64_t)nx * ny};
+    DegridArgs da{P->groups, P->n_groups, grid, Vg, cf, nx, ny, (int64_t)nx * ny, mix,
+                  accum ? 1 : 0};
     bool po = P->po != 0;
     bool sm = h_max <= kDegridSmallH;
     switch (precision) {

@@ -359,6 +359,7 @@ struct TileArgs {
     int64_t pol_stride;   // nx * ny
     int32_t n_chunks;
     int32_t set;          // GRID_SET: exclusive chunks overwrite their whole tile
+    uint32_t mix;         // Mueller pass: bit q * NPOL + p adds pol q's sum into slot p (0: none)
 };
 
 // Thread t of a 256-thread workgroup clears column t % 32 of tile `tile`.
@@ -446,10 +447,26 @@ __global__ __launch_bounds__(256) void k_grid_tile(TileArgs a) {
             ti.by = gm.pv - h;
             ti.S = 2 * h + 1;
             ti.conj = gm.conj;
-            ti.sc = gm.sc;
+            ti.sc = a.cf.scale[(int64_t)gm.fg * a.cf.n_w + gm.k];
             ti.h = h;
             items[t] = ti;
-            for (int p = 0; p < NPOL; ++p) avs[t * NPOL + p] = Av[(int64_t)g * NPOL + p];
+            if (a.mix == 0) {
+                for (int p = 0; p < NPOL; ++p) avs[t * NPOL + p] = Av[(int64_t)g * NPOL + p];
+            } else {
+                // a Mueller pass: slot p takes the sum of the correlations q
+                // whose element M[q][p] is the pass's kind
+                cpx<T> in[NPOL];
+                for (int q = 0; q < NPOL; ++q) in[q] = Av[(int64_t)g * NPOL + q];
+                for (int p = 0; p < NPOL; ++p) {
+                    cpx<T> v = {(T)0, (T)0};
+                    for (int q = 0; q < NPOL; ++q)
+                        if ((a.mix >> (q * NPOL + p)) & 1u) {
+                            v.x += in[q].x;
+                            v.y += in[q].y;
+                        }
+                    avs[t * NPOL + p] = v;
+                }
+            }
             if (PO) gms[t] = gm;
         }
         __syncthreads();
@@ -906,16 +923,17 @@ static hipError_t grid_np(const TileArgs &ta, int64_t n_blocks, int npol, bool p
 
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
                        int precision, int32_t npol, int32_t nx, int32_t ny, int32_t mode,
-                       bool det, hipStream_t s) {
+                       bool det, uint32_t mix, hipStream_t s) {
     const bool set = mode == GRID_SET;
-    if (sep_gridder(P, cf, mode, det)) return launch_grid_sep(P, cf, A, grid, precision, npol, nx, ny, set, s);
+    if (mix == 0 && sep_gridder(P, cf, mode, det))
+        return launch_grid_sep(P, cf, A, grid, precision, npol, nx, ny, set, s);
     // GRID_SET: one more workgroup per tile clears the tiles without pairs
     const int64_t nc = P->n_chunks + (set ? P->n_tiles : 0);
     if (nc == 0) return hipSuccess;
     TileArgs ta{P->groups, P->tp_group, P->chunk_start, P->chunk_tile, P->chunk_excl,
                 P->chunk_order, P->tile_state, A, grid, cf, nx, ny, (nx + kTile - 1) / kTile,
                 (ny + kTile - 1) / kTile, (int64_t)nx * ny, (int32_t)P->n_chunks,
-                set ? 1 : 0};
+                set ? 1 : 0, mix};
     bool po = P->po != 0;
     bool psf = mode == GRID_PSF;
     det = det && !psf;

@@ -115,14 +115,67 @@ lr_status check_spec(const lr_cf_spec *s) {
     if ((s->terms & LR_TERM_A) && !(s->dish_m > 0.0)) return fail(LR_E_ARG, "dish_m must be positive");
     if (s->screen_m < 0 || (s->screen_m & 1)) return fail(LR_E_ARG, "screen_m must be even (0 = auto)");
     if (elem_bytes_of(s->storage) == 0) return fail(LR_E_DTYPE, "unknown storage type");
+    if (s->pol_beam < 0 || s->pol_beam > 3) return fail(LR_E_ARG, "pol_beam must be in 0..3");
+    if (s->pol_beam) {
+        if (!(s->terms & LR_TERM_A)) return fail(LR_E_ARG, "a polarised beam needs the A term");
+        if (!(std::fabs(s->beam_ellipticity) < 0.5))
+            return fail(LR_E_ARG, "beam_ellipticity must lie in (-0.5, 0.5)");
+        if (!(std::fabs(s->beam_leakage) <= 10.0))
+            return fail(LR_E_ARG, "beam_leakage must lie in [-10, 10]");
+    }
     return LR_OK;
+}
+
+// Mueller kinds of the polarised beam: element M[q][p] = J[q1][p1] J[q2][p2]
+// of J = [[E_X, d], [d, E_Y]] (q = 2 q1 + q2) is the product of two of
+// E_X, E_Y, d; its order is the number of d factors.  Kinds in table order:
+// E_X^2, E_Y^2, E_X E_Y, E_X d, E_Y d, d^2.  Elements of order >= pol_beam
+// are left out (-1).  The scalar beam has one kind on the diagonal.
+int32_t n_kind_of(int32_t pol_beam) {
+    static const int32_t n[4] = {1, 3, 5, 6};
+    return n[pol_beam];
+}
+
+void kind_map(int32_t pol_beam, int32_t npol, int32_t out[16]) {
+    for (int i = 0; i < 16; ++i) out[i] = -1;
+    if (!pol_beam) {
+        for (int q = 0; q < npol; ++q) out[q * 4 + q] = 0;
+        return;
+    }
+    enum { EX = 0, EY = 1, D = 2 };
+    auto el = [](int a, int b) { return a != b ? D : (a == 0 ? EX : EY); };
+    for (int q = 0; q < 4; ++q)
+        for (int p = 0; p < 4; ++p) {
+            int f1 = el(q >> 1, p >> 1), f2 = el(q & 1, p & 1);
+            int order = (f1 == D) + (f2 == D);
+            if (order >= pol_beam) continue;
+            if (f1 > f2) std::swap(f1, f2);
+            int kind;
+            if (f1 == EX && f2 == EX) kind = 0;
+            else if (f1 == EY && f2 == EY) kind = 1;
+            else if (f1 == EX && f2 == EY) kind = 2;
+            else if (f1 == EX && f2 == D) kind = 3;
+            else if (f1 == EY && f2 == D) kind = 4;
+            else kind = 5;
+            out[q * 4 + p] = kind;
+        }
+}
+
+// The mask of one Mueller pass: bit q * npol + p when M[q][p] has `kind`.
+uint32_t kind_mask(const lr_cf *cf, int32_t kind, int32_t npol) {
+    uint32_t m = 0;
+    for (int q = 0; q < npol; ++q)
+        for (int p = 0; p < npol; ++p)
+            if (cf->kind_of[q * 4 + p] == kind) m |= 1u << (q * npol + p);
+    return m;
 }
 
 struct Geometry {
     std::vector<int32_t> h;
     int32_t M = 0, hmax = 0;
     std::vector<int64_t> plane_off;
-    int64_t n_elems = 0;
+    int64_t n_elems = 0;            // per kind
+    int32_t n_kind = 1;
     size_t off_h = 0, off_po = 0, off_exp = 0, off_scale = 0, off_table = 0, total = 0;
 };
 
@@ -130,6 +183,9 @@ lr_status geometry(const lr_cf_spec *s, const lr_grid_spec *g, Geometry &G) {
     lr_status st;
     if ((st = check_spec(s)) != LR_OK) return st;
     if ((st = check_grid(g)) != LR_OK) return st;
+    if (s->pol_beam && g->npol != 4)
+        return fail(LR_E_ARG, "a polarised beam needs npol = 4 (XX, XY, YX, YY)");
+    G.n_kind = n_kind_of(s->pol_beam);
     G.h = half_widths(s->n_w, s->h_min, s->h_max);
     G.hmax = *std::max_element(G.h.begin(), G.h.end());
     int32_t smax = 2 * G.hmax + 1;
@@ -152,9 +208,9 @@ lr_status geometry(const lr_cf_spec *s, const lr_grid_spec *g, Geometry &G) {
     G.off_h = 0;
     G.off_po = al256(sizeof(int32_t) * s->n_w);
     G.off_exp = G.off_po + al256(sizeof(int64_t) * np);
-    G.off_scale = G.off_exp + al256(sizeof(int32_t) * np);
-    G.off_table = G.off_scale + al256(sizeof(float) * np);
-    G.total = G.off_table + (size_t)G.n_elems * eb;
+    G.off_scale = G.off_exp + al256(sizeof(int32_t) * np * G.n_kind);
+    G.off_table = G.off_scale + al256(sizeof(float) * np * G.n_kind);
+    G.total = G.off_table + (size_t)G.n_elems * G.n_kind * eb;
     return LR_OK;
 }
 
@@ -177,6 +233,14 @@ CFView view_of(const lr_cf *cf) {
     return v;
 }
 
+// The view of one Mueller kind: its table and its planes' scales.
+CFView view_kind(const lr_cf *cf, int32_t kind) {
+    CFView v = view_of(cf);
+    v.table = (const char *)cf->d_table + (size_t)kind * cf->kind_elems * cf->elem_bytes;
+    v.scale = cf->d_scale + (size_t)kind * cf->spec.n_fg * cf->spec.n_w;
+    return v;
+}
+
 lr_cf *make_handle(const lr_cf_spec *s, const lr_grid_spec *g, const Geometry &G, void *buf) {
     lr_cf *cf = new (std::nothrow) lr_cf;
     if (!cf) return nullptr;
@@ -187,7 +251,10 @@ lr_cf *make_handle(const lr_cf_spec *s, const lr_grid_spec *g, const Geometry &G
     cf->M = G.M;
     cf->h = G.h;
     cf->plane_off = G.plane_off;
-    cf->n_elems = G.n_elems;
+    cf->n_kind = G.n_kind;
+    cf->kind_elems = G.n_elems;
+    cf->n_elems = G.n_elems * G.n_kind;
+    kind_map(s->pol_beam, g->npol, cf->kind_of);
     cf->elem_bytes = elem_bytes_of(s->storage);
     cf->header_bytes = G.off_table;
     cf->total_bytes = G.total;
@@ -364,7 +431,8 @@ lr_status build_plan(const lr_cf *cf, const lr_vis *v, int psf, void *buf, size_
     double dv_dm = 1.0 / ((double)cf->grid.ny * cf->grid.cell_m);
     // largest-first chunk order for kernel tables up to the size of the
     // last-level cache (256 MB)
-    const bool lpt = (size_t)cf->n_elems * cf->elem_bytes <= ((size_t)256 << 20);
+    // one kind's table is read per gridder pass
+    const bool lpt = (size_t)cf->kind_elems * cf->elem_bytes <= ((size_t)256 << 20);
     e = build_plan_device(P, b, L, v->uvw, d_cc, g, kl, view_of(cf), v->ant1, v->ant2,
                           v->nant, v->ant_dlm, du_dl, dv_dm, chunk_pairs(), kChunkCells, lpt, s);
     if (e == hipErrorInvalidValue)
@@ -488,6 +556,10 @@ lr_status lr_cf_build(const lr_cf_spec *spec, const lr_grid_spec *grid, void *cf
     a.cell_m = grid->cell_m;
     a.c_ps = M_PI * spec->ps_support / 2.0;
     a.dish_m = spec->dish_m;
+    a.pol_beam = spec->pol_beam;
+    a.kind = 0;
+    a.eta = spec->beam_ellipticity;
+    a.kappa = spec->beam_leakage;
     e = launch_cf_build(cf, a, work, s);
     if (e != hipSuccess) { delete cf; return dev_fail(e, "CF build"); }
     *out = cf;
@@ -514,10 +586,17 @@ void lr_cf_free(lr_cf *cf) { delete cf; }
 lr_status lr_cf_scale_exponents(const lr_cf *cf, int32_t *exps, lr_stream stream) {
     if (!cf || !exps) return fail(LR_E_ARG, "NULL argument");
     hipStream_t s = (hipStream_t)stream;
-    size_t n = (size_t)cf->spec.n_fg * cf->spec.n_w;
+    size_t n = (size_t)cf->spec.n_fg * cf->spec.n_w * cf->n_kind;
     hipError_t e = hipMemcpyAsync(exps, cf->d_exp, n * sizeof(int32_t), hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) return dev_fail(e, "read scale exponents");
+    return LR_OK;
+}
+
+lr_status lr_cf_kinds(const lr_cf *cf, int32_t *n_kind, int32_t *kind_of) {
+    if (!cf) return fail(LR_E_ARG, "cf handle is NULL");
+    if (n_kind) *n_kind = cf->n_kind;
+    if (kind_of) std::copy(cf->kind_of, cf->kind_of + 16, kind_of);
     return LR_OK;
 }
 
@@ -689,6 +768,8 @@ lr_status lr_ps_taper(const lr_cf *cf, int32_t n, void *out, lr_stream stream) {
 
 lr_status lr_pb_image(const lr_cf *cf, const double *fg_weight, void *out, lr_stream stream) {
     if (!cf || !fg_weight || !out) return fail(LR_E_ARG, "NULL argument");
+    if (cf->n_kind > 1)
+        return fail(LR_E_CF, "the weight image is defined for a scalar beam (pol_beam = 0)");
     hipError_t e = launch_pb_image(cf, fg_weight, (double *)out, (hipStream_t)stream);
     if (e != hipSuccess) return dev_fail(e, "weight image");
     return LR_OK;
@@ -860,12 +941,33 @@ static lr_status static_scratch(void **out) {
     return LR_OK;
 }
 
+// The gridder launches of one call: one for a scalar beam; one per Mueller
+// kind otherwise, each with its table and the mask that sums the
+// correlations of its elements into their grid pols (the first pass may
+// write a fresh grid, the later ones add).
+static hipError_t grid_passes(const lr_cf *cf, const lr_plan *P, const void *A, void *grid,
+                              lr_precision precision, int32_t npol, int mode, bool det,
+                              hipStream_t s) {
+    if (cf->n_kind == 1)
+        return launch_grid(P, view_of(cf), A, grid, precision, npol, cf->grid.nx, cf->grid.ny,
+                           mode, det, 0u, s);
+    hipError_t e = hipSuccess;
+    for (int32_t kind = 0; kind < cf->n_kind && e == hipSuccess; ++kind) {
+        const int m = (kind > 0 && mode == GRID_SET) ? GRID_ADD : mode;
+        e = launch_grid(P, view_kind(cf, kind), A, grid, precision, npol, cf->grid.nx,
+                        cf->grid.ny, m, det, kind_mask(cf, kind, npol), s);
+    }
+    return e;
+}
+
 static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision precision,
                              void *grid, double *sumwt, int64_t *counters, void *work,
                              size_t work_bytes, lr_stream stream, int mode) {
     const int psf = mode == GRID_PSF ? 1 : 0;
     lr_status st = check_vis(cf, vis, !psf, true);
     if (st != LR_OK) return st;
+    if (psf && cf->n_kind > 1)
+        return fail(LR_E_CF, "the PSF takes a table of one scalar beam (pol_beam = 0)");
     if ((st = check_precision(cf, precision)) != LR_OK) return st;
     if (!grid) return fail(LR_E_ARG, "grid is NULL");
     if (!work && work_bytes) return fail(LR_E_ARG, "work is NULL");
@@ -907,15 +1009,12 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
             e = launch_presum_det(P, va, precision, A, done, pieces, counters, s);
         if (e == hipSuccess) {
             prof.begin();
-            e = launch_grid(P, view_of(cf), A, grid, precision, vis->npol, cf->grid.nx,
-                            cf->grid.ny, mode, true, s);
+            e = grid_passes(cf, P, A, grid, precision, vis->npol, mode, true, s);
             prof.end();
         }
         if (e != hipSuccess) return dev_fail(e, "grid");
         return LR_OK;
     }
-    // the separable small-support gridder writes whole tiles itself: no
-    // shared tiles to clear first
     // the separable small-support gridder writes whole tiles itself; only
     // tiles it splits into several parts are cleared first (GRID_SET)
     const CFView view = view_of(cf);
@@ -928,8 +1027,7 @@ static lr_status grid_common(const lr_cf *cf, const lr_vis *vis, lr_precision pr
         e = launch_presum(P, va, precision, A, sumwt, counters, cf->grid.nplane, s);
     if (e == hipSuccess) {
         prof.begin();
-        e = launch_grid(P, view, A, grid, precision, vis->npol, cf->grid.nx,
-                        cf->grid.ny, mode, false, s);
+        e = grid_passes(cf, P, A, grid, precision, vis->npol, mode, false, s);
         prof.end();
     }
     if (e != hipSuccess) return dev_fail(e, psf ? "psf" : "grid");
@@ -996,8 +1094,17 @@ lr_status lr_degrid(const lr_cf *cf, lr_vis *vis, lr_precision precision, const 
     void *Vg = (char *)work + used;
     ProfileScope prof(s);
     prof.begin();
-    hipError_t e = launch_degrid(P, view_of(cf), grid, Vg, precision, vis->npol, cf->grid.nx,
-                                 cf->grid.ny, h_max_of(cf), s);
+    hipError_t e = hipSuccess;
+    if (cf->n_kind == 1) {
+        e = launch_degrid(P, view_of(cf), grid, Vg, precision, vis->npol, cf->grid.nx,
+                          cf->grid.ny, h_max_of(cf), 0u, false, s);
+    } else {
+        // one pass per Mueller kind, each adding its elements' gathers
+        for (int32_t kind = 0; kind < cf->n_kind && e == hipSuccess; ++kind)
+            e = launch_degrid(P, view_kind(cf, kind), grid, Vg, precision, vis->npol,
+                              cf->grid.nx, cf->grid.ny, h_max_of(cf),
+                              kind_mask(cf, kind, vis->npol), kind > 0, s);
+    }
     prof.end();
     if (e == hipSuccess) e = launch_expand(P, Vg, vis->vis, vis->weight, precision, vis->npol, s);
     if (e == hipSuccess && counters)

@@ -118,8 +118,11 @@ struct lr_cf {
     lr_grid_spec grid;
     int32_t M;
     std::vector<int32_t> h;
-    std::vector<int64_t> plane_off;     // element offsets
-    int64_t n_elems;
+    std::vector<int64_t> plane_off;     // element offsets (kind 0)
+    int64_t n_elems;                    // elements of every kind
+    int32_t n_kind;                     // Mueller kinds held (1: scalar beam)
+    int64_t kind_elems;                 // elements per kind
+    int32_t kind_of[16];                // kind of M[q][p] (q * 4 + p), -1 none
     size_t elem_bytes;
     size_t header_bytes, total_bytes;
     char *blob;                         // device

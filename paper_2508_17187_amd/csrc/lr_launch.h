@@ -42,6 +42,8 @@ hipError_t build_plan_device(lr_plan *P, char *buf, const PlanLayout &L, const d
 struct CFBuildArgs {
     int32_t M, O, nx, ny, terms;
     double cell_l, cell_m, c_ps, dish_m;
+    int32_t pol_beam, kind;     // polarised beam: the Mueller kind of the screen
+    double eta, kappa;          // beam ellipticity and leakage
 };
 size_t cf_work_bytes(int32_t M, int32_t O, int32_t h_max);
 hipError_t launch_cf_build(const lr_cf *cf, const CFBuildArgs &a, void *work, hipStream_t s);
@@ -67,9 +69,11 @@ hipError_t launch_counts(const lr_plan *P, const void *weight, int precision, in
 enum { GRID_ADD = 0, GRID_PSF = 1, GRID_SET = 2 };
 // det: deterministic order (one workgroup per tile, no atomic flushes; not
 // for GRID_PSF)
+// mix (Mueller passes; 0 = none): bit q * npol + p set when correlation q's
+// group sums go into grid pol p in this pass.
 hipError_t launch_grid(const lr_plan *P, const CFView &cf, const void *A, void *grid,
                        int precision, int32_t npol, int32_t nx, int32_t ny, int32_t mode,
-                       bool det, hipStream_t s);
+                       bool det, uint32_t mix, hipStream_t s);
 // Whether launch_grid takes the separable small-support gridder (one
 // workgroup per tile, every cell written once): then GRID_SET needs no
 // clearing of shared tiles beforehand.
@@ -89,9 +93,11 @@ hipError_t launch_grid_setup(const lr_plan *P, void *A, size_t a_bytes, double *
                              bool sep, hipStream_t s);
 // h_max: widest half-width of the table (small supports take the
 // four-groups-per-wavefront degridder)
+// mix (Mueller passes; 0 = none): bit q * npol + p set when grid pol p's
+// gather adds into correlation q; accum adds to Vg instead of writing it.
 hipError_t launch_degrid(const lr_plan *P, const CFView &cf, const void *grid, void *Vg,
                          int precision, int32_t npol, int32_t nx, int32_t ny, int32_t h_max,
-                         hipStream_t s);
+                         uint32_t mix, bool accum, hipStream_t s);
 hipError_t launch_expand(const lr_plan *P, const void *Vg, void *vis, const void *weight,
                          int precision, int32_t npol, hipStream_t s);
 

@@ -44,7 +44,9 @@ class CFSpec(C.Structure):
     _fields_ = [("terms", C.c_uint32), ("oversample", C.c_int32), ("ps_support", C.c_int32),
                 ("n_w", C.c_int32), ("w_max", C.c_double), ("h_min", C.c_int32),
                 ("h_max", C.c_int32), ("n_fg", C.c_int32), ("fg_hz", C.c_void_p),
-                ("dish_m", C.c_double), ("screen_m", C.c_int32), ("storage", C.c_int32)]
+                ("dish_m", C.c_double), ("screen_m", C.c_int32), ("storage", C.c_int32),
+                ("pol_beam", C.c_int32), ("beam_ellipticity", C.c_double),
+                ("beam_leakage", C.c_double)]
 
 
 class VisDesc(C.Structure):
@@ -64,6 +66,7 @@ EXPORTS = {
     "lr_cf_free": (None, [C.c_void_p]),
     "lr_cf_scale_exponents": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lr_cf_layout": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
+    "lr_cf_kinds": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p]),
     "lr_plan_bytes": (C.c_size_t, [C.c_void_p, C.c_void_p, C.c_int]),
     "lr_plan_build": (C.c_int, [C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
                                 C.c_void_p, C.c_void_p]),
@@ -198,21 +201,32 @@ class CF:
                                   po.ctypes.data_as(C.c_void_p)))
         return off.value, eb.value, ne.value, po
 
-    def plane_host(self, fg, k):
-        """One (fg, k) plane of an FP64 or FP32 table as complex128 on the
-        host, flat in table order (test hook for tables too big to copy
-        whole)."""
+    def kinds(self):
+        """(n_kind, kind_of [4][4]): the Mueller kinds the table holds and the
+        kind of each element M[q][p] (-1: not held)."""
+        n = C.c_int32()
+        km = np.zeros(16, np.int32)
+        _check(lib().lr_cf_kinds(self.handle, C.byref(n), km.ctypes.data_as(C.c_void_p)))
+        return n.value, km.reshape(4, 4)
+
+    def plane_host(self, fg, k, kind=0):
+        """One (fg, k) plane of Mueller kind `kind` of an FP64 or FP32 table as
+        complex128 on the host, flat in table order (test hook for tables too
+        big to copy whole)."""
         off, eb, ne, po = self.layout()
         if eb not in (8, 16):
             raise ValueError("plane_host reads FP64 / FP32 tables")
+        ke = ne // self.kinds()[0]
         i = fg * self.spec.n_w + k
-        end = int(po[i + 1]) if i + 1 < len(po) else int(ne)
-        raw = self.blob[off + eb * int(po[i]):off + eb * end].cpu().numpy()
+        end = int(po[i + 1]) if i + 1 < len(po) else ke
+        b0 = off + eb * (kind * ke + int(po[i]))
+        raw = self.blob[b0:b0 + eb * (end - int(po[i]))].cpu().numpy()
         return raw.view(np.complex128 if eb == 16 else np.complex64).astype(np.complex128)
 
     def table_host(self):
         """The stored table decoded to complex128 on the host (test hook):
-        fp16 / bf16 entries are divided by their plane's 2^e."""
+        fp16 / bf16 entries are divided by their plane's 2^e.  Kinds follow
+        one another."""
         off, eb, ne, po = self.layout()
         raw = self.blob[off:off + eb * ne].cpu().numpy()
         if eb == 16:
@@ -228,14 +242,18 @@ class CF:
             im = (u & 0xFFFF0000).astype(np.uint32).view(np.float32).astype(np.float64)
         out = re + 1j * im
         ex = self.scale_exponents()
-        bounds = list(po) + [ne]
-        for i in range(len(po)):
-            out[bounds[i]:bounds[i + 1]] = np.ldexp(out[bounds[i]:bounds[i + 1]].real, -int(ex[i])) \
-                + 1j * np.ldexp(out[bounds[i]:bounds[i + 1]].imag, -int(ex[i]))
+        nk = self.kinds()[0]
+        ke = ne // nk
+        bounds = list(po) + [ke]
+        for kind in range(nk):
+            for i in range(len(po)):
+                a, b = kind * ke + bounds[i], kind * ke + bounds[i + 1]
+                e = -int(ex[kind * len(po) + i])
+                out[a:b] = np.ldexp(out[a:b].real, e) + 1j * np.ldexp(out[a:b].imag, e)
         return out
 
     def scale_exponents(self, stream=None):
-        n = self.spec.n_fg * self.spec.n_w
+        n = self.spec.n_fg * self.spec.n_w * self.kinds()[0]
         out = np.zeros(n, np.int32)
         _check(lib().lr_cf_scale_exponents(self.handle, out.ctypes.data_as(C.c_void_p),
                                            _stream(stream)))

@@ -16,7 +16,10 @@ def cf_spec(c, storage):
     return dict(terms=int(c.terms), oversample=int(c.oversample), ps_support=int(c.ps_support),
                 n_w=int(c.n_w), w_max=float(c.w_max), h_min=int(c.h_min), h_max=int(c.h_max),
                 n_fg=int(len(c.fg_hz)), fg_hz=np.asarray(c.fg_hz, np.float64),
-                dish_m=float(c.dish_m), screen_m=int(c.screen_m), storage=int(storage))
+                dish_m=float(c.dish_m), screen_m=int(c.screen_m), storage=int(storage),
+                pol_beam=int(getattr(c, "pol_beam", 0)),
+                beam_ellipticity=float(getattr(c, "beam_ellipticity", 0.0)),
+                beam_leakage=float(getattr(c, "beam_leakage", 0.0)))
 
 
 def build_cf(wl, precision, device="cuda", stream=None):
