@@ -19,6 +19,7 @@ in the FP32 form.
 
 import argparse
 import ctypes as C
+import gc
 import json
 import os
 import sys
@@ -896,12 +897,18 @@ def serving_bench(n_jobs=256, rate=20.0, budget_gb=16.0, slots=4, form="f32", jo
     srv = S.Server(exe, hbm_budget=int(budget_gb * (1 << 30)), n_slots=slots)
     t0 = time.perf_counter()
 
+    def consume(fut):
+        # the client takes each result as its job completes and lets it go
+        # (results held to the end would pin host memory for the whole run)
+        if fut.exception() is None:
+            fut.result().result = None
+
     def submit_all():
         for j, ta in zip(jobs, arrivals):
             d = t0 + ta - time.perf_counter()
             if d > 0:
                 time.sleep(d)
-            srv.submit(j)
+            srv.submit(j).add_done_callback(consume)
 
     th = threading.Thread(target=submit_all)
     th.start()
@@ -1214,6 +1221,10 @@ def run_legs(args, ev, want, out):
         out["large_image_streamed"] = large_image_streamed(args.steps, args.warmup, ev)
         log("  ", json.dumps(out["large_image_streamed"]))
         torch.cuda.empty_cache()
+        # hand the leg's 16 GB of pinned host buffers back to the system
+        gc.collect()
+        if hasattr(torch._C, "_host_emptyCache"):
+            torch._C._host_emptyCache()
     if want("serving") and args.serving_jobs > 0:
         log("serving stream of %d jobs" % args.serving_jobs)
         jobs = serving_jobs(args.serving_jobs, 20.0, "f32")

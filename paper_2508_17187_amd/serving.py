@@ -438,9 +438,18 @@ class GPUExecutor:
                 v.vis = torch.empty(tuple(wt.shape), dtype=self.cplx, device=self.dev)
                 lr.lr_degrid(cf, v, self.p, grid, stream=s)
                 dev_out = v.vis
-            out = torch.empty(dev_out.shape, dtype=dev_out.dtype, pin_memory=True)
-            out.copy_(dev_out, non_blocking=True)
-            s.synchronize()
+            try:
+                out = torch.empty(dev_out.shape, dtype=dev_out.dtype, pin_memory=True)
+            except RuntimeError:
+                # pinned memory exhausted (results the caller still holds):
+                # a pageable copy, slower but bounded by host memory only
+                out = None
+            if out is not None:
+                out.copy_(dev_out, non_blocking=True)
+                s.synchronize()
+            else:
+                s.synchronize()
+                out = dev_out.cpu()
         return out.numpy()
 
 
