@@ -136,6 +136,107 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
     if (lane == 0) store_group<T, NPOL>(a, g, tot);
 }
 
+// FP32 grids without a pointing phasor: lanes over pairs of neighbouring
+// taps of a footprint row, so that one 16-byte load brings two grid values
+// of a pol and one 16-byte (8-byte with FP16 / BF16 values) load two kernel
+// values: half the vector-memory instructions of one tap per load, whose
+// address processing bounds the one-tap kernel.  Pairs start at even grid
+// columns (the row's first pair may begin one column before the
+// footprint); with nx even a pair never crosses a grid row.  A pair's tap
+// outside the footprint row reads its neighbour in the table (the row
+// before or after, or the blob's padding past the table's end) and adds
+// zero.
+typedef float f32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+constexpr int kDegridPairs = 2;      // pairs per lane in flight
+
+template <int ST, int NPOL, bool RE>
+__global__ __launch_bounds__(256) void k_degrid_pair(DegridArgs a) {
+    constexpr int E = CFRaw<ST>::bytes;                 // 8: f32, 4: f16 / bf16 pair
+    typedef typename std::conditional<E == 8, f32x4_a8, u32x2_a4>::type Raw2;
+    typedef typename CFRaw<ST>::R Raw;
+    constexpr int NT = kDegridPairs;
+    const int lane = threadIdx.x & 63;
+    const int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + uni(threadIdx.x >> 6);
+    if (g >= a.n_groups) return;
+    const GroupMeta gm = a.groups[g];
+    const int h = uni(gm.h);
+    const int S = 2 * h + 1;
+    const float sc = a.cf.scale[(int64_t)gm.fg * a.cf.n_w + gm.k];
+    const bool cj = uni(gm.conj) != 0;
+    const int lead = (uni(gm.pu) - h) & 1;              // footprint starts at an odd column
+    const int W2 = (S + lead + 1) >> 1;                 // pairs per footprint row
+    const int NP = S * W2;
+    // kernel bytes from tap (0, -lead); grid cell (0, -lead) of pol 0
+    const char *cfb = (const char *)a.cf.table + (uni64(gm.cf_off) - lead) * E;
+    const int64_t corner = uni64(gm.cell) - (int64_t)h * a.nx - h - lead;
+    const int64_t pstride = a.pol_stride * 8;
+    const char *gbp[NPOL];
+    for (int p = 0; p < NPOL; ++p)
+        gbp[p] = (const char *)a.grid + uni64(corner * 8 + p * pstride);
+    const int row = a.nx * 8;
+    const int dr = 64 / W2, dc = 64 - dr * W2;
+    int r = lane / W2, c = lane - (lane / W2) * W2;
+    cpx<float> sum[NPOL];
+    for (int p = 0; p < NPOL; ++p) sum[p] = {0.f, 0.f};
+    for (int t0 = 0; t0 < NP; t0 += 64 * NT) {
+        Raw2 cr[NT];
+        f32x4_a8 gv[NT][NPOL];
+        bool ok[NT], v0[NT], v1[NT];
+        for (int u = 0; u < NT; ++u) {
+            const int pp = t0 + u * 64 + lane;
+            ok[u] = pp < NP;
+            const int tu0 = 2 * c - lead;
+            v0[u] = ok[u] && tu0 >= 0;
+            v1[u] = ok[u] && tu0 + 1 < S;
+            // lanes past the footprint load pair 0 (in bounds) and add nothing
+            const uint32_t co = ok[u] ? (uint32_t)(r * S + 2 * c) * (uint32_t)E : 0u;
+            const uint32_t go = ok[u] ? (uint32_t)(r * row + c * 16) : 0u;
+            cr[u] = *(const Raw2 *)(cfb + co);
+            for (int p = 0; p < NPOL; ++p) gv[u][p] = *(const f32x4_a8 *)(gbp[p] + go);
+            c += dc;
+            r += dr;
+            if (c >= W2) {
+                c -= W2;
+                ++r;
+            }
+        }
+        for (int u = 0; u < NT; ++u) {
+            // the pair's two kernel values, zero outside the footprint row
+            cpx<float> k0, k1;
+            if constexpr (E == 8) {
+                k0 = {cr[u].x, cr[u].y};
+                k1 = {cr[u].z, cr[u].w};
+            } else {
+                k0 = CFRaw<ST>::decode((Raw)cr[u].x, sc);
+                k1 = CFRaw<ST>::decode((Raw)cr[u].y, sc);
+            }
+            if (RE) k0.y = k1.y = 0.f;
+            if (!v0[u]) k0 = {0.f, 0.f};
+            if (!v1[u]) k1 = {0.f, 0.f};
+            if (cj) {
+                k0.y = -k0.y;
+                k1.y = -k1.y;
+            }
+            for (int p = 0; p < NPOL; ++p) {
+                const cpx<float> g0 = {gv[u][p].x, gv[u][p].y}, g1 = {gv[u][p].z, gv[u][p].w};
+                if constexpr (RE) {
+                    sum[p].x = fmaf(k0.x, g0.x, sum[p].x);
+                    sum[p].y = fmaf(k0.x, g0.y, sum[p].y);
+                    sum[p].x = fmaf(k1.x, g1.x, sum[p].x);
+                    sum[p].y = fmaf(k1.x, g1.y, sum[p].y);
+                } else {
+                    cmac_conj(sum[p], k0, g0);
+                    cmac_conj(sum[p], k1, g1);
+                }
+            }
+        }
+    }
+    cpx<float> tot[NPOL];
+    for (int p = 0; p < NPOL; ++p) tot[p] = {wave_sum(sum[p].x), wave_sum(sum[p].y)};
+    if (lane == 0) store_group<float, NPOL>(a, g, tot);
+}
+
 // Small supports (S <= 2 kDegridSmallH + 1): a 7 x 7 footprint would leave
 // most of a wavefront idle, so 16 lanes take one group (four groups per
 // wavefront), four taps per lane in flight, and reduce over their 16 lanes.
@@ -218,6 +319,13 @@ static hipError_t degrid_t(const DegridArgs &da, bool po, bool small, hipStream_
         return hipGetLastError();
     }
     dim3 grd(nblk(da.n_groups, 4));
+    if constexpr (sizeof(T) == 4) {
+        if (!po) {
+            if (re) hipLaunchKernelGGL((k_degrid_pair<ST, NPOL, true>), grd, blk, 0, s, da);
+            else hipLaunchKernelGGL((k_degrid_pair<ST, NPOL, false>), grd, blk, 0, s, da);
+            return hipGetLastError();
+        }
+    }
     if (po) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, true, false>), grd, blk, 0, s, da);
     else if (re) hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false, true>), grd, blk, 0, s, da);
     else hipLaunchKernelGGL((k_degrid<T, ST, NPOL, false, false>), grd, blk, 0, s, da);

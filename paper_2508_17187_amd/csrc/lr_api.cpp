@@ -170,6 +170,8 @@ uint32_t kind_mask(const lr_cf *cf, int32_t kind, int32_t npol) {
     return m;
 }
 
+constexpr size_t kTablePad = 256;
+
 struct Geometry {
     std::vector<int32_t> h;
     int32_t M = 0, hmax = 0;
@@ -210,7 +212,9 @@ lr_status geometry(const lr_cf_spec *s, const lr_grid_spec *g, Geometry &G) {
     G.off_exp = G.off_po + al256(sizeof(int64_t) * np);
     G.off_scale = G.off_exp + al256(sizeof(int32_t) * np * G.n_kind);
     G.off_table = G.off_scale + al256(sizeof(float) * np * G.n_kind);
-    G.total = G.off_table + (size_t)G.n_elems * G.n_kind * eb;
+    // zeroed padding after the table: the paired degridder's loads of a
+    // footprint row's last tap may read one element past the table
+    G.total = G.off_table + (size_t)G.n_elems * G.n_kind * eb + kTablePad;
     return LR_OK;
 }
 
@@ -561,6 +565,8 @@ lr_status lr_cf_build(const lr_cf_spec *spec, const lr_grid_spec *grid, void *cf
     a.eta = spec->beam_ellipticity;
     a.kappa = spec->beam_leakage;
     e = launch_cf_build(cf, a, work, s);
+    if (e == hipSuccess)
+        e = launch_zero((char *)cf->d_table + (size_t)cf->n_elems * cf->elem_bytes, kTablePad, s);
     if (e != hipSuccess) { delete cf; return dev_fail(e, "CF build"); }
     *out = cf;
     return LR_OK;
