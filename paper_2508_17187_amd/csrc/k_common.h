@@ -262,6 +262,11 @@ __device__ __forceinline__ void divmod_small(int t, int S, float invS, int &q, i
 // (gfx9 encoding: vmcnt bits 3:0 and 15:14, expcnt 6:4, lgkmcnt 11:8).
 constexpr int kWaitVm0 = 0x0F70;
 
+// Two neighbouring complex64 (or FP16 / BF16 pair) kernel or grid values in
+// one load: 8-byte (4-byte) alignment is all the paired loads can promise.
+typedef float f32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
+typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
+
 static inline unsigned nblk(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace lr

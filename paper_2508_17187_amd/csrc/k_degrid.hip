@@ -146,8 +146,6 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
 // outside the footprint row reads its neighbour in the table (the row
 // before or after, or the blob's padding past the table's end) and adds
 // zero.
-typedef float f32x4_a8 __attribute__((ext_vector_type(4), aligned(8)));
-typedef uint32_t u32x2_a4 __attribute__((ext_vector_type(2), aligned(4)));
 constexpr int kDegridPairs = 2;      // pairs per lane in flight
 
 template <int ST, int NPOL, bool RE>
