@@ -313,7 +313,10 @@ lr_status lr_grid_static(const lr_cf *cf, const lr_vis *vis, lr_precision precis
  * for kept samples; flagged and dropped samples are written as 0.  No
  * weights enter the sum.  counters may be NULL.  With a Mueller table
  * (pol_beam > 0) correlation q sums conj(Ct_qp) over the grid pols p its
- * row of the sparse matrix holds (one pass per kind). */
+ * row of the sparse matrix holds (one pass per kind).  The grid must hold
+ * finite values: with FP32 grids the gather reads two cells per load and may
+ * take in one cell beyond a footprint row's end with weight 0, so an Inf or
+ * NaN there would reach the sample. */
 lr_status lr_degrid(const lr_cf *cf, lr_vis *vis, lr_precision precision, const void *grid,
                     int64_t *counters, void *work, size_t work_bytes, lr_stream stream);
 
