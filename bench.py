@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "visibilities gridded+degridded/sec, FP32/FP16-CF vs FP64; p50/p99 job latency"
 PEAK = {"f64": 78.6e12, "f32": 157.3e12, "f16cf": 157.3e12, "bf16cf": 157.3e12}
 HBM_PEAK = 8.0e12
+N_CU, CLOCK_HZ = 256, 2.4e9
 
 
 def log(*a):
@@ -688,6 +689,13 @@ def large_image_roofline(res):
            # every group reads its S x S sub-kernel: bytes the kernel must
            # fetch when no table plane stays in cache between groups
            "kernel_tap_bytes_per_launch": res["taps"] * ELEM[form] / n}
+    # bytes the kernel's vector loads return per launch: every tap's kernel
+    # value, and for the degridder the four pols' grid values of the tap
+    # (the gridder keeps its grid in registers), per clock and CU
+    gbytes = 16 if form == "f64" else 8
+    vm = res["taps"] * (ELEM[form] + (4 * gbytes if k == "degridder" else 0)) / n
+    out["vmem_bytes_per_launch"] = vm
+    out["vmem_bytes_per_clk_per_cu"] = vm / (t / n) / (N_CU * CLOCK_HZ)
     if traffic is not None:
         out["traffic_rate_gbps"] = traffic / (t / n) / 1e9
         out["traffic_frac_of_hbm_peak"] = traffic / (t / n) / HBM_PEAK
