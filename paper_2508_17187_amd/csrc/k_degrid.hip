@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_degrid(DegridArgs a) {
 // outside the footprint row reads its neighbour in the table (the row
 // before or after, or the blob's padding past the table's end) and adds
 // zero.
-constexpr int kDegridPairs = 2;      // pairs per lane in flight
+constexpr int kDegridPairs = 3;      // pairs per lane in flight
 
 template <int ST, int NPOL, bool RE>
 __global__ __launch_bounds__(256) void k_degrid_pair(DegridArgs a) {
