@@ -191,6 +191,31 @@ def check_grid(wl, ocf, form):
     assert c_ref[0] > 0 and c_ref[1] > 0 and c_ref[2] > 0
 
 
+@pytest.mark.parametrize("form", ["f64", "f32"])
+@pytest.mark.parametrize("plan", [False, True], ids=["transient", "plan"])
+def test_sumwt_default_mode_matches_oracle(awp, form, plan):
+    """lr_sumwt in the default (scheduling-dependent) order: FP64 sums of the
+    kept weights per (plane, pol) and the class counts, added to what the
+    outputs held (the oracle sums the weights the GPU was given: FP32
+    weights rounded first)."""
+    wl, ocf = awp
+    p = PREC[form]
+    cf = W.build_cf(wl, p)
+    v = W.device_vis(wl, p)
+    if plan:
+        v.plan = lr.Plan(cf, v)
+    sw = torch.full((wl.grid.nplane, wl.grid.npol), 0.25, dtype=torch.float64, device=DEV)
+    cnt = torch.tensor([5, 6, 7], dtype=torch.int64, device=DEV)
+    lr.lr_sumwt(cf, v, p, sw, counters=cnt)
+    torch.cuda.synchronize()
+    w = wl.weight if form == "f64" else wl.weight.astype(np.float32).astype(np.float64)
+    s_ref, c_ref = Problem.from_workload(wl, ocf).sumwt(w)
+    assert np.array_equal(cnt.cpu().numpy(), c_ref + np.array([5, 6, 7]))
+    got = sw.cpu().numpy() - 0.25
+    assert np.max(np.abs(got - s_ref)) <= 1e-12 * np.abs(s_ref).max()
+    assert c_ref[0] > 0 and c_ref[1] > 0 and c_ref[2] > 0
+
+
 @pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
 def test_grid_parity(awp, form):
     wl, ocf = awp
