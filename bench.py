@@ -820,6 +820,76 @@ def image_bench(wl, form, steps, ev):
     return out
 
 
+def autograd_bench(steps, warmup):
+    """The differentiable degrid on the A+W data with pointing offsets (351
+    baselines x 600 dumps x 64 channels x 4 pols = 53,913,600 visibilities,
+    Airy A terms in 8 frequency groups, 32 w-planes, 4096^2 x 4 model of
+    1000 point components): one iteration is chi^2 (F, degrid, residual;
+    Eq. ImChisq) and its gradient through the hand-written gridding adjoint
+    (grid, F^dagger; Eq. ResIm), in FP32 and FP64, timed with the degrid
+    and adjoint calls on their own; the FP32 gradient against the FP64 one."""
+    import torch
+    import synth
+    from paper_2508_17187_amd import lr
+    from paper_2508_17187_amd import workload as W
+    from paper_2508_17187_amd.autograd import DegridOp, centred_fft2, chi2
+    wl = synth.config3_awproj(dft_device="cuda")
+    g = wl.grid
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(3100)
+    base = torch.zeros((g.nplane, g.npol, g.ny, g.nx), dtype=torch.float64, device="cuda")
+    iy = torch.randint(g.ny // 8, g.ny - g.ny // 8, (1000,), generator=gen, device="cuda")
+    ix = torch.randint(g.nx // 8, g.nx - g.nx // 8, (1000,), generator=gen, device="cuda")
+    base[0, 0, iy, ix] = 1e-3 * torch.rand(1000, generator=gen, device="cuda",
+                                           dtype=torch.float64)
+    base[0, 3] = base[0, 0]
+    n = int(wl.nsamples)
+    out = {"workload": "A+W projection with pointing offsets: 351 baselines x 600 dumps x "
+                       "64 channels x 4 pols = 53,913,600 visibilities; Airy A terms in 8 "
+                       "frequency groups, 32 w-planes, supports 17-65, O=20; 4096x4096x4 "
+                       "model", "samples": n, "forms": {}}
+    grads = {}
+
+    def timed(fn, k):
+        for _ in range(warmup):
+            fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        for _ in range(k):
+            r = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / k, r
+
+    for f in ("f32", "f64"):
+        p = lr.PRECISIONS[f]
+        cf = W.build_cf(wl, p)
+        v = W.device_vis(wl, p)
+        op = DegridOp(cf, v, p)
+        img = base.to(op.rdt).requires_grad_(True)
+
+        def step():
+            (gr,) = torch.autograd.grad(chi2(img, op, v.vis, v.weight), img)
+            return gr
+
+        ms, gr = timed(step, steps)
+        grads[f] = gr.detach().double()
+        grid = centred_fft2(base.to(op.cdt))
+        ms_d, vm = timed(lambda: op.degrid(grid), steps)
+        ms_g, _ = timed(lambda: op.grid_adjoint(vm), steps)
+        out["forms"][f] = {"ms_per_iteration": ms, "vis_per_s": n / (ms * 1e-3),
+                           "degrid_call_ms": ms_d, "grid_adjoint_call_ms": ms_g,
+                           "kernel_calls_vis_per_s": n / ((ms_d + ms_g) * 1e-3)}
+        del cf, v, op, img, grid, vm
+        torch.cuda.empty_cache()
+    out["speedup_f32_vs_f64"] = out["forms"]["f32"]["vis_per_s"] / out["forms"]["f64"]["vis_per_s"]
+    out["gradient_rel_rms_f32_vs_f64"] = float(
+        (torch.linalg.vector_norm(grads["f32"] - grads["f64"])
+         / torch.linalg.vector_norm(grads["f64"])).item())
+    return out
+
+
 def serving_jobs(n_jobs, rate, form):
     """The serving stream (configuration 4): visibility counts log-uniform
     in [1e4, 2e7] (4 pols, one 3 GHz channel), grids of 512^2 .. 4096^2 x 4
@@ -1056,8 +1126,8 @@ def main():
                     help="jobs in the serving stream (0 = skip it)")
     ap.add_argument("--legs", default="all",
                     help="comma list of legs after the headline (wproj, image, cf_cache, "
-                         "calibration, mosaic, deterministic, standard, standard_chunk, "
-                         "streamed, serving), 'all' or ''")
+                         "calibration, mosaic, deterministic, autograd, standard, "
+                         "standard_chunk, streamed, serving), 'all' or ''")
     ap.add_argument("--no-legs", dest="legs", action="store_const", const="",
                     help="only the large image (headline) and the CPU baseline")
     ap.add_argument("--no-large", action="store_true",
@@ -1201,6 +1271,11 @@ def run_legs(args, ev, want, out):
             log("deterministic order")
             out["deterministic"] = deterministic_bench(wl, "f32", args.steps)
         del wl
+        torch.cuda.empty_cache()
+    if want("autograd"):
+        log("differentiable degrid on the A+W data")
+        out["autograd"] = autograd_bench(args.steps, args.warmup)
+        log("  ", json.dumps(out["autograd"]))
         torch.cuda.empty_cache()
     if want("standard"):
         log("standard-kernel (PS) workloads")
