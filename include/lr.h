@@ -271,6 +271,13 @@ lr_status lr_set_profile_events(void *start, void *stop);
 
 /* ---- the hot path ------------------------------------------------------------ */
 
+/* Workspace of the visibility calls below (lr_grid, lr_grid_overwrite,
+ * lr_degrid, lr_make_psf, lr_sumwt): `work` is device scratch of at least
+ * lr_workspace_bytes(op, ...) bytes for the same arguments (the per-group
+ * sums or values, and a transient plan when vis->plan is NULL); a smaller
+ * work_bytes gives LR_E_WORKSPACE before anything is enqueued.  The
+ * scratch is free again once the call's work has run on its stream. */
+
 /* Gridding G (Eq. IMAGE-MOD): grid[P][pol][p_v + t_v][p_u + t_u] +=
  * Ct(o, t) phi(t) W V for every kept sample, Ct = C or conj C (w < 0),
  * phi = pointing phasor (Eq. CIJ) when ant ids and offsets are given.
