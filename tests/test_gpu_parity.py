@@ -117,6 +117,52 @@ def test_map_bitexact_ties_and_edges():
     assert keep.sum() > 1000 and (~keep).sum() > 100
 
 
+@pytest.mark.parametrize("form", ["f64", "f32"])
+def test_grid_and_degrid_with_footprints_at_the_grid_edges(form):
+    """Samples dense near the edges of a 64 x 64 grid, so that kept
+    footprints touch the first and last rows and columns (the FP32
+    degridder's two-cell loads there start at column 0 or end at column
+    nx - 1): G and D against the oracle."""
+    rng = np.random.default_rng(12)
+    nx, O = 64, 20
+    cell = 4.0 * synth.ARCSEC
+    freq = np.array([2.2e9, 3.3e9, 3.9e9])
+    du_m = synth.C_LIGHT / freq[-1] / (nx * cell)
+    u = rng.uniform(-34, 34, 4000) * du_m
+    v = rng.uniform(-34, 34, 4000) * du_m
+    w_max = 5e4
+    w = rng.uniform(-1, 1, 4000) * w_max * synth.C_LIGHT / freq[-1]
+    wl = synth.tiny_workload(nx=nx, ny=nx, cell_arcsec=4.0, oversample=O, n_w=8, h_min=2,
+                             h_max=5, terms=TERM_PS | TERM_W, nchan=3, n_time=2)
+    wl.obs.uvw = np.stack([u, v, w], 1)
+    wl.obs.freq_hz = freq
+    wl.cf.w_max = w_max
+    wl.vis = rng.standard_normal((4000, 3, 4)) + 1j * rng.standard_normal((4000, 3, 4))
+    wl.weight = rng.uniform(0.5, 1.5, (4000, 3, 4))
+    ocf = oracle.build_cf(wl.grid, wl.cf)
+    pr = Problem.from_workload(wl, ocf)
+    m = pr.map()
+    keep = m[..., 6] == 1
+    h = oracle.half_widths(wl.cf.n_w, wl.cf.h_min, wl.cf.h_max)[m[..., 4]]
+    for lo, hi in ((m[..., 0] - h, m[..., 0] + h), (m[..., 1] - h, m[..., 1] + h)):
+        assert (keep & (lo == 0)).sum() > 10 and (keep & (hi == nx - 1)).sum() > 10
+    assert (~keep).sum() > 100
+    p = PREC[form]
+    cf = W.build_cf(wl, p)
+    vd = W.device_vis(wl, p)
+    g = W.empty_grid(wl, p)
+    lr.lr_grid(cf, vd, p, g)
+    e = rel(g.cpu().numpy(), pr.grid(wl.vis, wl.weight))
+    x = rng.standard_normal((1, 4, nx, nx)) + 1j * rng.standard_normal((1, 4, nx, nx))
+    lr.lr_degrid(cf, vd, p, torch.as_tensor(x, device=DEV).to(g.dtype))
+    ref = pr.degrid(x, wl.weight)
+    got = vd.vis.cpu().numpy()
+    e2 = rel(got, ref)
+    say("edges", form, e, e2)
+    assert e <= TOL[form] and e2 <= TOL[form]
+    assert np.all(got[ref == 0] == 0)
+
+
 def test_map_bitexact_config1():
     wl = synth.config1_plain()
     ocf = oracle.build_cf(wl.grid, wl.cf)
