@@ -117,7 +117,7 @@ def test_map_bitexact_ties_and_edges():
     assert keep.sum() > 1000 and (~keep).sum() > 100
 
 
-@pytest.mark.parametrize("form", ["f64", "f32"])
+@pytest.mark.parametrize("form", ["f64", "f32", "f16cf", "bf16cf"])
 def test_grid_and_degrid_with_footprints_at_the_grid_edges(form):
     """Samples dense near the edges of a 64 x 64 grid, so that kept
     footprints touch the first and last rows and columns (the FP32
