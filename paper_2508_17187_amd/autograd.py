@@ -70,17 +70,45 @@ class Degrid(torch.autograd.Function):
         return ctx.op.grid_adjoint(grad_v.to(ctx.op.cdt)), None
 
 
+_CHECKER = {}
+
+
+def _checker(ny, nx, dtype, device):
+    """(-1)^(y + x) over an ny x nx plane, and the same times (-1)^((ny + nx)/2)."""
+    key = (ny, nx, dtype, str(device))
+    if key not in _CHECKER:
+        y = torch.arange(ny, device=device).view(ny, 1)
+        x = torch.arange(nx, device=device).view(1, nx)
+        c = (1 - 2 * ((y + x) % 2)).to(dtype)
+        _CHECKER[key] = (c, c * (1 - 2 * (((ny + nx) // 2) % 2)))
+    return _CHECKER[key]
+
+
+def _real_dtype(t):
+    return t.real.dtype if t.is_complex() else t.dtype
+
+
 def centred_fft2(img):
-    """F: grid[v][u] = sum_pix img[m][l] exp(-2 pi i (u l + v m)), pixel n/2 at 0."""
-    return torch.fft.fftshift(torch.fft.fft2(torch.fft.ifftshift(img, dim=(-2, -1))),
-                              dim=(-2, -1))
+    """F: grid[v][u] = sum_pix img[m][l] exp(-2 pi i (u l + v m)), pixel n/2 at 0.
+    For even sizes the centring shifts are a (-1)^(y + x) factor on either
+    side of the plain transform (with the sign i^(ny + nx)): two elementwise
+    passes instead of four rolls and a copy."""
+    ny, nx = img.shape[-2:]
+    if ny % 2 or nx % 2:
+        return torch.fft.fftshift(torch.fft.fft2(torch.fft.ifftshift(img, dim=(-2, -1))),
+                                  dim=(-2, -1))
+    c, cs = _checker(ny, nx, _real_dtype(img), img.device)
+    return torch.fft.fft2(img * c) * cs
 
 
 def centred_ifft2(grid):
-    """F^dagger, unnormalised."""
-    n = grid.shape[-1] * grid.shape[-2]
-    return torch.fft.fftshift(torch.fft.ifft2(torch.fft.ifftshift(grid, dim=(-2, -1))),
-                              dim=(-2, -1)) * n
+    """F^dagger, unnormalised (the same centring factors, and no 1/n)."""
+    ny, nx = grid.shape[-2:]
+    if ny % 2 or nx % 2:
+        return torch.fft.fftshift(torch.fft.ifft2(torch.fft.ifftshift(grid, dim=(-2, -1))),
+                                  dim=(-2, -1)) * (nx * ny)
+    c, cs = _checker(ny, nx, _real_dtype(grid), grid.device)
+    return torch.fft.ifft2(grid * c, norm="forward") * cs
 
 
 def predict(image, op, gamma=None):
