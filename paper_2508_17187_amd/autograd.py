@@ -120,7 +120,27 @@ def predict(image, op, gamma=None):
     return Degrid.apply(grid, op)
 
 
+class WeightedResidual(torch.autograd.Function):
+    """sum W |V_obs - V|^2 in three passes (the residual, its weighting and
+    one dot product) with a one-pass backward: for a real loss of complex V
+    PyTorch's gradient is 2 dL/d conj(V) = -2 W (V_obs - V)."""
+
+    @staticmethod
+    def forward(ctx, v, vis_obs, weight):
+        r = vis_obs - v
+        wr = r * weight
+        ctx.save_for_backward(r, wr)
+        return torch.vdot(r.reshape(-1), wr.reshape(-1)).real
+
+    @staticmethod
+    def backward(ctx, g):
+        r, wr = ctx.saved_tensors
+        gv = -2.0 * g * wr if ctx.needs_input_grad[0] else None
+        go = 2.0 * g * wr if ctx.needs_input_grad[1] else None
+        gw = g * (r.real ** 2 + r.imag ** 2) if ctx.needs_input_grad[2] else None
+        return gv, go, gw
+
+
 def chi2(image, op, vis_obs, weight, gamma=None):
     """Eq. ImChisq: sum W |V_obs - D F gamma I|^2."""
-    r = vis_obs - predict(image, op, gamma)
-    return (weight * (r.real ** 2 + r.imag ** 2)).sum()
+    return WeightedResidual.apply(predict(image, op, gamma), vis_obs, weight)
