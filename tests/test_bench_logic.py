@@ -42,7 +42,7 @@ def test_traffic_files_match_their_sources():
     """Every committed traffic file was taken on the sources as they are
     (otherwise bench.py reports traffic as null)."""
     found = 0
-    for w in ("large_image", "wproj2048", "standard2048", "standard_chunk"):
+    for w in ("large_image", "large_image_f16cf", "wproj2048", "standard2048", "standard_chunk"):
         path = os.path.join(ROOT, "profiles", w + "_traffic.json")
         tr = json.load(open(path))
         for kernel, k in tr["kernels"].items():
